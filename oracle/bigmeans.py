@@ -1,0 +1,166 @@
+"""Algorithm 1 (competitive stochastic-sample-size Big-means), oracle side.
+
+Test infrastructure only.  Follows Section 4.2 (Algorithm 1 and the text
+after it) and Section 4.3, with the parameters of Section 5.
+
+Structure (rounds t < T, workers w, passes q < p, global pass g = t*p + q):
+  * each worker starts with all k centroids degenerate and f_hat = +inf;
+  * at the start of every round a worker draws its sample size s_w; if it
+    already has an incumbent and the size changed, its f_hat is re-evaluated
+    on a fresh sample of the new size (Section 4.2: any change of s_w
+    requires recomputing the incumbent's objective);
+  * each pass draws a new sample S_w, re-seeds the degenerate centroids with
+    greedy K-means++ on S_w, runs K-means from the incumbent, and accepts the
+    result only if its objective on S_w is strictly below f_hat (a NaN is
+    never accepted); every acceptance appends s_w to the list L;
+  * at the end s_opt = mean of L (Section 4.2: the simple mean, rounded half
+    up to an integer), one shared sample of size s_opt re-scores every
+    worker's incumbent, the worker with the smallest value wins (lowest
+    worker on ties), and every point of X is assigned to its centroids.
+
+Workers are independent apart from L; running them in lockstep rounds, as
+here, is one valid interleaving.  The BINS size policy reads L's statistics
+from earlier rounds only, which keeps it deterministic.
+
+Size policies (the paper draws s_w uniformly in [s_min, s_max]):
+  UNIFORM     s_min + mulhi(w0, s_max - s_min + 1)
+  FIXED       s_min (s_min == s_max)
+  LOGUNIFORM  floor(exp(ln a + u(w0) * (ln(b + 1) - ln a))) clamped to [a, b]
+  BINS        round 0 as LOGUNIFORM; later rounds choose one of 5 equal-width
+              bins of ln s with probability proportional to (a_i + 1)/(n_i + 2)
+              (a_i acceptances and n_i passes seen in bin i so far), then draw
+              log-uniformly inside the bin.
+with w = B((t, 0, 0, 0), key(seed, worker, SIZE)).
+"""
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import kmeans, rng
+
+SIZE_UNIFORM, SIZE_FIXED, SIZE_LOGUNIFORM, SIZE_BINS = 0, 1, 2, 3
+N_BINS = 5
+
+
+@dataclass
+class Params:
+    k: int
+    workers: int
+    rounds_T: int
+    passes_p: int = 10
+    s_min: int = 0
+    s_max: int = 0
+    size_policy: int = SIZE_UNIFORM
+    max_iter: int = 300
+    tol: float = 1e-4
+    n_candidates: int = 3
+    seed: int = 0
+
+
+def paper_size_range(s, m):
+    """Section 5: s_min = 0.5 s (rounded up), s_max = min(2 s, m)."""
+    return (int(s) + 1) // 2, min(2 * int(s), int(m))
+
+
+def _log_edges(a, b):
+    la = math.log(a)
+    return la, (math.log(b + 1) - la)
+
+
+def draw_size(params, worker, t, bin_stats):
+    """Sample size of `worker` for round t, and the bin (0..4) it falls in."""
+    a, b = int(params.s_min), int(params.s_max)
+    w = rng.philox_block_scalar((t, 0, 0, 0),
+                                rng.stream_key(params.seed, worker, rng.PURPOSE_SIZE))
+    pol = params.size_policy
+    if pol == SIZE_UNIFORM:
+        return a + rng.mulhi(w[0], b - a + 1), 0
+    if pol == SIZE_FIXED:
+        return a, 0
+    la, width = _log_edges(a, b)
+    if pol == SIZE_LOGUNIFORM or (pol == SIZE_BINS and t == 0):
+        u = rng.u01(w[0])
+        s = int(math.floor(math.exp(la + u * width)))
+        return min(max(s, a), b), min(N_BINS - 1, int(u * N_BINS))
+    if pol == SIZE_BINS:
+        weights = [(bin_stats["acc"][i] + 1.0) / (bin_stats["passes"][i] + 2.0)
+                   for i in range(N_BINS)]
+        total = math.fsum(weights)
+        x = rng.u01(w[1]) * total
+        acc, i_bin = 0.0, N_BINS - 1
+        for i in range(N_BINS):
+            acc += weights[i]
+            if x < acc:
+                i_bin = i
+                break
+        v = la + (i_bin + rng.u01(w[2])) * (width / N_BINS)
+        s = int(math.floor(math.exp(v)))
+        return min(max(s, a), b), i_bin
+    raise ValueError("unknown size policy")
+
+
+def _sample(X, s, seed, worker, purpose, g):
+    idx = rng.sample_indices(X.shape[0], s, seed, worker, purpose, g)
+    return X[idx]
+
+
+def bigmeans_run(X, params, keep_trace=False):
+    """Run Algorithm 1 on X (m x n).  Returns a dict with C_best, Y, s_opt,
+    f_full, the winning worker, the list L and per-round statistics."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    m, n = X.shape
+    P = params
+    W, k = P.workers, P.k
+    if not (1 <= k <= P.s_min <= P.s_max <= m):
+        raise ValueError("need 1 <= k <= s_min <= s_max <= m")
+    C = [np.zeros((k, n)) for _ in range(W)]
+    deg = [np.ones(k, dtype=bool) for _ in range(W)]
+    fhat = [math.inf] * W
+    s_cur = [None] * W
+    L = []                                  # (round, worker, pass, s, bin)
+    bin_stats = {"acc": [0] * N_BINS, "passes": [0] * N_BINS}
+    lloyd_dists = 0
+    lloyd_iters = 0
+    rounds = []
+    for t in range(P.rounds_T):
+        round_acc = [0] * N_BINS
+        round_passes = [0] * N_BINS
+        for w in range(W):
+            s_new, b = draw_size(P, w, t, bin_stats)
+            if fhat[w] < math.inf and s_new != s_cur[w]:
+                S_re = _sample(X, s_new, P.seed, w, rng.PURPOSE_RECALC, t)
+                fhat[w] = kmeans.objective(S_re, C[w])
+            s_cur[w] = s_new
+            for q in range(P.passes_p):
+                g = t * P.passes_p + q
+                S = _sample(X, s_new, P.seed, w, rng.PURPOSE_SAMPLE, g)
+                C0, _, _ = kmeans.kmeanspp(S, C[w], deg[w], P.n_candidates, P.seed, w, g)
+                res = kmeans.lloyd(S, C0, P.max_iter, P.tol)
+                lloyd_iters += res["iters"] + 1
+                lloyd_dists += (res["iters"] + 1) * s_new * k
+                round_passes[b] += 1
+                if res["f"] < fhat[w]:
+                    C[w], deg[w], fhat[w] = res["C"], res["deg"], res["f"]
+                    L.append((t, w, q, s_new, b))
+                    round_acc[b] += 1
+        for i in range(N_BINS):
+            bin_stats["acc"][i] += round_acc[i]
+            bin_stats["passes"][i] += round_passes[i]
+        if keep_trace:
+            rounds.append({"C": [c.copy() for c in C], "fhat": list(fhat), "s": list(s_cur)})
+    if L:
+        total = sum(e[3] for e in L)
+        s_opt = (total + len(L) // 2) // len(L)
+    else:
+        s_opt = P.s_max
+    S_fin = _sample(X, s_opt, P.seed, rng.FINAL_WORKER, rng.PURPOSE_FINAL, 0)
+    f_fin = [kmeans.objective(S_fin, C[w]) if fhat[w] < math.inf else math.inf
+             for w in range(W)]
+    best = min(range(W), key=lambda w: (not (f_fin[w] == f_fin[w]), f_fin[w], w))
+    Y, d1 = kmeans.assign(X, C[best])
+    return {"C_best": C[best], "Y": Y, "s_opt": s_opt, "f_full": math.fsum(d1.tolist()),
+            "best_worker": best, "f_final_sample": f_fin, "L": L, "fhat": fhat,
+            "C_all": C, "deg_all": deg, "lloyd_dists": lloyd_dists,
+            "lloyd_iters": lloyd_iters, "rounds": rounds}
