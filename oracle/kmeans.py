@@ -126,9 +126,9 @@ def lloyd(S, C0, max_iter=300, tol=1e-4):
     """K-means (Lloyd) on sample S from initial centroids C0.
 
     Each iteration assigns every point to its nearest centre and evaluates
-    f = f(C, S); it stops when f_prev - f <= tol * f or when max_iter centroid
-    updates have been made, otherwise it moves each centroid to the mean of
-    its cluster.  Returns a dict with the final centroids C, their objective f,
+    f = f(C, S); it stops when f_prev - f <= tol * f, when f is not finite,
+    or when max_iter centroid updates have been made, otherwise it moves each
+    centroid to the mean of its cluster.  Returns a dict with the final centroids C, their objective f,
     the labels, the degenerate mask (empty clusters under the final
     assignment), the number of updates 'iters', and the objective trace.
     """
@@ -144,6 +144,8 @@ def lloyd(S, C0, max_iter=300, tol=1e-4):
         trace.append(f)
         counts = np.bincount(labels, minlength=k)
         if f_prev is not None and f_prev - f <= tol * f:
+            break
+        if not math.isfinite(f):      # NaN/inf points: the objective can never improve
             break
         if it >= max_iter:
             break
@@ -198,10 +200,14 @@ def kmeanspp(S, C, deg, n_cand, seed, worker, g):
                 i_c = int(np.searchsorted(prefix, tau, side="right"))
                 cands.append(i_c)
                 pots.append(math.fsum(np.minimum(D, sqdist_direct(S, S[i_c])).tolist()))
-            i_star = cands[int(np.argmin(pots))]
+            best = 0                      # smallest potential, lowest c on ties
+            for c in range(1, n_cand):
+                if pots[c] < pots[best]:
+                    best = c
+            i_star = cands[best]
         C[j] = S[i_star]
         dnew = sqdist_direct(S, S[i_star])
-        D = dnew if D is None else np.minimum(D, dnew)
+        D = dnew if D is None else np.minimum(D, dnew)   # NaN propagates into D and T
         deg[j] = False
         log.append({"centroid": j, "candidates": cands, "potentials": pots,
                     "total": T, "chosen": i_star})
