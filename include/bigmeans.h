@@ -1,0 +1,240 @@
+/*
+ * bigmeans.h - C ABI of the MI355X (gfx950) implementation of the hot path of
+ * competitive stochastic-sample-size Big-means (Mussabayev & Mussabayev,
+ * arXiv 2403.18766).
+ *
+ * The library computes, on one GPU:
+ *   - uniform random samples of the data without replacement (Section 4.1,
+ *     "shaking"; Algorithm 1, the sample S_w of each pass);
+ *   - greedy K-means++ seeding of degenerate centroids on a sample
+ *     (Section 3; Section 4.1; Section 5: three candidate points);
+ *   - Lloyd K-means iterations on a sample (Algorithm 1; Section 5: at most
+ *     300 iterations, relative tolerance 1e-4);
+ *   - the MSSC objective f(C, X) of Eq. (1) with nearest-centre labels;
+ *   - Algorithm 1 end to end (bm_bigmeans_run).
+ *
+ * Conventions for every call
+ *   - Point, sample, centroid, label, index and flag arrays are DEVICE
+ *     pointers on the context's device, row-major and densely packed
+ *     (row stride = n floats), owned by the caller; the library never frees
+ *     them.  Float arrays must be 4-byte aligned (16-byte alignment enables
+ *     vector loads).
+ *   - Scalar outputs (double f, iteration counts, result structs) are HOST
+ *     pointers.  Calls with a host scalar output synchronise the context's
+ *     stream before returning; calls without one only enqueue work.
+ *   - All work is enqueued on the stream given to bm_create (0 = the legacy
+ *     default stream).  The library owns only the workspace it allocates in
+ *     bm_create/bm_reserve; no other call allocates device memory.
+ *   - Return value: BM_OK (0) or a negative bm_status.  bm_strerror(ctx)
+ *     describes the last error of that context.  No call aborts and no C++
+ *     exception crosses this interface.
+ *   - A context is used by one host thread at a time.
+ *
+ * Randomness (the paper fixes none).  Every random draw comes from the
+ * Philox4x64-10 block function B(ctr, key) of Salmon et al. (SC'11) with
+ * key = (seed, (worker << 8) | purpose).  Sample element i is the i-th output
+ * of a 4-round Feistel permutation of [0, 4^h) (h = max(1, ceil(ceil(log2 m)/2)))
+ * walked into [0, m), with round keys B((g,0,0,0), key) and round function
+ * SplitMix64-finaliser(R xor K_r).  K-means++ step t of global pass g uses
+ * B((t, g, 0, 0), key); the size draw of round t uses B((t, 0, 0, 0), key).
+ */
+#ifndef BIGMEANS_H
+#define BIGMEANS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define BM_API __attribute__((visibility("default")))
+#else
+#define BM_API
+#endif
+
+#define BM_VERSION 1
+
+typedef struct bm_ctx bm_ctx;
+
+typedef enum bm_status {
+  BM_OK = 0,
+  BM_E_ARG = -1,       /* invalid argument (sizes, null pointer, alignment) */
+  BM_E_NOMEM = -2,     /* workspace allocation failed, or call exceeds reserved sizes */
+  BM_E_HIP = -3,       /* a HIP runtime call failed */
+  BM_E_NONFINITE = -4, /* the objective is NaN or infinite; outputs are still written */
+  BM_E_STATE = -5      /* context not usable (no device, destroyed workspace) */
+} bm_status;
+
+typedef enum bm_precision { BM_FP32 = 0, BM_BF16 = 1 } bm_precision;
+
+typedef enum bm_size_policy {
+  BM_SIZE_UNIFORM = 0,    /* s uniform integer in [s_min, s_max] (Algorithm 1) */
+  BM_SIZE_FIXED = 1,      /* s = s_min (s_min == s_max) */
+  BM_SIZE_LOGUNIFORM = 2, /* floor(exp(ln a + u (ln(b+1) - ln a))), clamped to [a, b] */
+  BM_SIZE_BINS = 3        /* round 0 log-uniform; later rounds pick one of 5 log-width bins
+                             with weight (acc_i + 1)/(passes_i + 2), then log-uniform inside */
+} bm_size_policy;
+
+typedef enum bm_purpose {
+  BM_PURPOSE_SIZE = 1,
+  BM_PURPOSE_SAMPLE = 2,
+  BM_PURPOSE_KMPP = 3,
+  BM_PURPOSE_RECALC = 4,
+  BM_PURPOSE_FINAL = 5
+} bm_purpose;
+
+#define BM_FINAL_WORKER 0xFFFFFFu
+
+/* Library version (BM_VERSION).  Needs no device. */
+BM_API int bm_version(void);
+
+/* Create a context on HIP device `device`, enqueueing on `hip_stream`
+ * (a hipStream_t, or NULL for the default stream).  *out receives the
+ * context.  Returns BM_E_STATE if the device cannot be used. */
+BM_API int bm_create(int device, void* hip_stream, bm_ctx** out);
+
+/* Release the context and its workspace.  NULL is ignored. */
+BM_API void bm_destroy(bm_ctx* ctx);
+
+/* Message of the last error of ctx (never NULL; "" if none). */
+BM_API const char* bm_strerror(const bm_ctx* ctx);
+
+/* Allocate workspace for up to max_jobs concurrent samples of at most max_s
+ * points in max_n dimensions with max_k centroids.  Later calls with larger
+ * sizes grow it; calls with sizes within the reservation never allocate.
+ * Calls that need more than the reservation reserve it themselves first
+ * (allocation happens there, not in the kernels' hot loop). */
+BM_API int bm_reserve(bm_ctx* ctx, int64_t max_s, int32_t max_n, int32_t max_k,
+                      int32_t max_jobs);
+
+/* Random sample without replacement (Section 4.1; Algorithm 1, "random
+ * sample of size s_w from X").
+ *   X       device, m x n FP32 rows.
+ *   idx_out device, s int32: idx_out[i] = row of X taken as sample element i.
+ *   S_out   device, s x n FP32 (may be NULL): S_out[i] = X[idx_out[i]].
+ * Requires 1 <= s <= m < 2^31, n >= 1.  Enqueue only. */
+BM_API int bm_sample(bm_ctx* ctx, const float* X, int64_t m, int32_t n, int64_t s,
+                     uint64_t seed, uint32_t worker, uint32_t purpose, uint64_t g,
+                     int32_t* idx_out, float* S_out);
+
+/* Greedy K-means++ (Section 3; Section 4.1: only centroids of degenerate
+ * clusters are re-initialised; Section 5: three candidates).  Every centroid
+ * j with degenerate[j] != 0 is replaced, in ascending j, by a point of S; the
+ * others are kept and define the initial D^2 weights.  With no kept centroid
+ * the first pick is uniform.  Each later pick draws n_candidates points with
+ * probability proportional to D^2 and keeps the one with the smallest
+ * potential sum_i min(D_i, ||S_i - cand||^2).
+ *   S          device, s x n FP32.
+ *   C          device, k x n FP32, in/out.
+ *   degenerate device, k uint8, in/out (all cleared on return).
+ *   picks_out  device, k x 4 int32 or NULL: for re-seeded centroid j,
+ *              {chosen sample index, candidate 0, 1, 2} (-1 where unused);
+ *              rows of kept centroids are -1.
+ * Requires 1 <= k <= s, 1 <= n_candidates <= 3.  Enqueue only. */
+BM_API int bm_seed(bm_ctx* ctx, const float* S, int64_t s, int32_t n, int32_t k,
+                   float* C, uint8_t* degenerate, int32_t n_candidates,
+                   uint64_t seed, uint32_t worker, uint64_t g, int32_t* picks_out);
+
+/* Lloyd K-means on sample S from the centroids in C (Algorithm 1, "K-means
+ * clustering on S_w with initial centroids C_w").  Each iteration labels
+ * every point with its nearest centre (lowest index on ties) and evaluates
+ * f = f(C, S) in FP64 accumulation; it stops when f_prev - f <= tol * f,
+ * when f is not finite, or after max_iter centroid updates; otherwise each
+ * centroid moves to the mean of its cluster (an empty cluster keeps its
+ * centre).
+ *   S              device, s x n FP32.
+ *   C              device, k x n FP32, in: initial, out: final centroids.
+ *   f_out          host: f(C_out, S).
+ *   iters_out      host (or NULL): number of centroid updates made.
+ *   degenerate_out device, k uint8 (or NULL): 1 if cluster j is empty under
+ *                  the final assignment.
+ *   labels_out     device, s int32 (or NULL): final labels.
+ * prec must be BM_FP32.  Returns BM_E_NONFINITE if f is not finite.
+ * Synchronises the stream. */
+BM_API int bm_lloyd(bm_ctx* ctx, const float* S, int64_t s, int32_t n, int32_t k, float* C,
+                    int32_t max_iter, double tol, int32_t prec, double* f_out,
+                    int32_t* iters_out, uint8_t* degenerate_out, int32_t* labels_out);
+
+/* MSSC objective, Eq. (1): f(C, X) = sum_i min_j ||x_i - c_j||^2 with FP32
+ * distances and FP64 accumulation; labels_out[i] = argmin_j (lowest j on ties).
+ *   X             device, m x n FP32.     C device, k x n FP32.
+ *   f_out         host.
+ *   labels_out    device, m int32, or NULL.
+ *   near_ties_out host, or NULL: number of points whose two smallest squared
+ *                 distances d1 <= d2 satisfy d2 - d1 < 1e-5 d2.
+ * prec must be BM_FP32.  Returns BM_E_NONFINITE if f is not finite.
+ * Synchronises the stream. */
+BM_API int bm_objective(bm_ctx* ctx, const float* X, int64_t m, int32_t n, const float* C,
+                        int32_t k, int32_t prec, double* f_out, int32_t* labels_out,
+                        int64_t* near_ties_out);
+
+/* Parameters of Algorithm 1. */
+typedef struct bm_params {
+  int64_t m;           /* rows of X */
+  int64_t s_min;       /* sample-size range; Section 5 uses 0.5 s and min(2 s, m) */
+  int64_t s_max;
+  int32_t n;           /* dimension */
+  int32_t k;           /* clusters, 1 <= k <= s_min */
+  int32_t workers;     /* competing workers W */
+  int32_t rounds_T;    /* rounds (size draws) per worker */
+  int32_t passes_p;    /* passes per size draw (Section 5: 10) */
+  int32_t max_iter;    /* Lloyd update cap (Section 5: 300) */
+  int32_t n_candidates;/* K-means++ candidates (Section 5: 3) */
+  int32_t size_policy; /* bm_size_policy */
+  int32_t prec;        /* BM_FP32 */
+  int32_t batched;     /* 1: run all workers' passes together (default);
+                          0: one worker's sample per launch (reference plain path) */
+  double tol;          /* Lloyd relative tolerance (Section 5: 1e-4) */
+  uint64_t seed;
+} bm_params;
+
+typedef struct bm_result {
+  double f_full;        /* f(C_best, X) */
+  double f_best_sample; /* winner's objective on the shared final sample */
+  int64_t s_opt;        /* round-half-up mean of the list L of improving sizes */
+  int64_t improvements; /* |L| */
+  int64_t lloyd_dists;  /* sum over Lloyd runs of s * k * (assignment steps) */
+  int64_t lloyd_iters;  /* total assignment steps */
+  int32_t best_worker;
+  int32_t pad_;
+  double gpu_seconds;   /* device time of the whole run */
+  double lloyd_seconds; /* device time of the Lloyd phases */
+} bm_result;
+
+/* Per-round snapshot callback: after round `round` (0-based), C_all_dev holds
+ * the W incumbents (W x k x n FP32, device, valid during the call),
+ * fhat_host the W incumbent objectives, s_host the W sample sizes, and
+ * t_seconds the device time elapsed since the start of the run. */
+typedef void (*bm_trace_cb)(void* user, int32_t round, const float* C_all_dev,
+                            const double* fhat_host, const int64_t* s_host, double t_seconds);
+
+/* Algorithm 1 end to end on X (device, m x n FP32): per round and worker a
+ * size draw and, on a size change, re-evaluation of the incumbent on a fresh
+ * sample; p passes of sample -> K-means++ for degenerate centroids -> Lloyd
+ * -> strict-improvement acceptance (appending s_w to L); then
+ * s_opt = mean of L, a shared sample of size s_opt, the worker with the
+ * smallest objective on it, and the full assignment of X.
+ *   C_best_out device, k x n FP32.   Y_out device, m int32 (or NULL).
+ *   out        host.   cb/user optional.
+ * Synchronises the stream. */
+BM_API int bm_bigmeans_run(bm_ctx* ctx, const float* X, const bm_params* params,
+                           float* C_best_out, int32_t* Y_out, bm_result* out,
+                           bm_trace_cb cb, void* user);
+
+/* Host-only: the sample size of `worker` in round t under params' policy,
+ * given the BINS statistics so far (bin_acc/bin_passes: 5 counts each, may
+ * be NULL for other policies).  Writes the size and its bin (0..4).  Needs no
+ * device. */
+BM_API int bm_draw_size(const bm_params* params, uint32_t worker, int32_t t,
+                        const int64_t* bin_acc, const int64_t* bin_passes,
+                        int64_t* s_out, int32_t* bin_out);
+
+/* Host-only: Philox4x64-10 block B(ctr, key) -> out[4].  Needs no device. */
+BM_API void bm_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BIGMEANS_H */

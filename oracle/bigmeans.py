@@ -87,7 +87,9 @@ def draw_size(params, worker, t, bin_stats):
     if pol == SIZE_BINS:
         weights = [(bin_stats["acc"][i] + 1.0) / (bin_stats["passes"][i] + 2.0)
                    for i in range(N_BINS)]
-        total = math.fsum(weights)
+        total = 0.0
+        for wt in weights:              # the weights' sum, added in bin order
+            total += wt
         x = rng.u01(w[1]) * total
         acc, i_bin = 0.0, N_BINS - 1
         for i in range(N_BINS):

@@ -1,0 +1,1029 @@
+// Host side of libbigmeans: context, workspace, the C ABI of
+// include/bigmeans.h and the driver of Algorithm 1.
+//
+// Every device buffer is allocated in bm_create / bm_reserve (or by a call
+// whose sizes exceed the reservation, before it enqueues any work); the
+// per-iteration and per-pass paths only enqueue kernels and small copies.
+// Small per-batch tables (sizes, tile maps, Feistel round keys) travel
+// host->device through a ring of pinned staging slots guarded by events.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/bigmeans.h"
+#include "bm_internal.h"
+#include "bm_rng.h"
+
+using bm::JobState;
+using bm::KppState;
+
+namespace {
+
+constexpr int kNumStage = 16;
+constexpr size_t kStageBytes = 256 * 1024;
+constexpr int kNBins = 5;
+
+int round_up4(int n) { return (n + 3) & ~3; }
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct bm_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+
+  // reservation
+  int64_t max_s = 0;
+  int max_n = 0, max_k = 0, max_jobs = 0, cpmax = 0;
+  int64_t max_chunks = 0;  // 256-point chunks per job
+  int64_t obj_chunks = 0;  // chunks reserved for a full-data objective
+
+  // device workspace
+  DevBuf S, idx, labels, Cp, cn, Cinc, deg_work, deg_inc, fhat, acc, cnt, tf, tnear, js, counter,
+      ndeg_acc, ntiles, sizes, tile_job, tile_idx, rkeys, seed_worker, absmax, scale, inv_scale,
+      fjob, nearjob, status, D, Dt, ks, todo, picks;
+  int64_t tile_cap = 0;  // entries of tile_job / tile_idx
+
+  // pinned staging ring
+  void* stage[kNumStage] = {};
+  hipEvent_t stage_ev[kNumStage] = {};
+  bool stage_used[kNumStage] = {};
+  int stage_next = 0;
+  // pinned readback area
+  void* rb = nullptr;
+  size_t rb_bytes = 0;
+
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
+
+  int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    err = buf;
+    return code;
+  }
+  int hip_fail(hipError_t e, const char* what) {
+    return fail(BM_E_HIP, "%s: %s", what, hipGetErrorString(e));
+  }
+};
+
+#define HIP_TRY(ctx, expr)                                      \
+  do {                                                          \
+    hipError_t e_ = (expr);                                     \
+    if (e_ != hipSuccess) return (ctx)->hip_fail(e_, #expr);    \
+  } while (0)
+
+#define BM_TRY(expr)              \
+  do {                            \
+    int r_ = (expr);              \
+    if (r_ != BM_OK) return r_;   \
+  } while (0)
+
+namespace {
+
+template <typename T>
+T* P(const DevBuf& b) {
+  return static_cast<T*>(b.p);
+}
+
+int dev_alloc(bm_ctx* c, DevBuf& b, size_t bytes) {
+  if (b.bytes >= bytes && b.p) return BM_OK;
+  if (b.p) {
+    (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  if (bytes == 0) bytes = 256;
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    return c->fail(BM_E_NOMEM, "hipMalloc(%zu bytes): %s", bytes, hipGetErrorString(e));
+  }
+  b.bytes = bytes;
+  return BM_OK;
+}
+
+void dev_free(DevBuf& b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+// Copy `bytes` from host memory to device memory through a pinned slot.
+int upload(bm_ctx* c, void* dst, const void* src, size_t bytes) {
+  if (bytes == 0) return BM_OK;
+  if (bytes > kStageBytes) return c->fail(BM_E_ARG, "upload of %zu bytes exceeds staging", bytes);
+  const int i = c->stage_next;
+  c->stage_next = (i + 1) % kNumStage;
+  if (c->stage_used[i]) HIP_TRY(c, hipEventSynchronize(c->stage_ev[i]));
+  std::memcpy(c->stage[i], src, bytes);
+  HIP_TRY(c, hipMemcpyAsync(dst, c->stage[i], bytes, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipEventRecord(c->stage_ev[i], c->stream));
+  c->stage_used[i] = true;
+  return BM_OK;
+}
+
+// Copy device memory to the pinned readback area and wait for it.
+int readback(bm_ctx* c, const void* src, size_t bytes, void* dst) {
+  if (bytes == 0) return BM_OK;
+  if (bytes > c->rb_bytes) {
+    if (c->rb) (void)hipHostFree(c->rb);
+    c->rb = nullptr;
+    HIP_TRY(c, hipHostMalloc(&c->rb, bytes, hipHostMallocDefault));
+    c->rb_bytes = bytes;
+  }
+  HIP_TRY(c, hipMemcpyAsync(c->rb, src, bytes, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  std::memcpy(dst, c->rb, bytes);
+  return BM_OK;
+}
+
+int reserve_impl(bm_ctx* c, int64_t max_s, int max_n, int max_k, int max_jobs) {
+  max_s = std::max<int64_t>(max_s, c->max_s);
+  max_n = std::max(max_n, c->max_n);
+  max_k = std::max(max_k, c->max_k);
+  max_jobs = std::max(max_jobs, c->max_jobs);
+  if (max_s == c->max_s && max_n == c->max_n && max_k == c->max_k && max_jobs == c->max_jobs &&
+      c->S.p)
+    return BM_OK;
+  // the stream may still use the old buffers
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const int cp = round_up4(max_n);
+  const int64_t mc = (max_s + bm::kWG - 1) / bm::kWG;
+  const size_t J = (size_t)max_jobs;
+  const size_t T = (size_t)bm::kMaxTiles;
+  BM_TRY(dev_alloc(c, c->S, J * max_s * cp * sizeof(float)));
+  BM_TRY(dev_alloc(c, c->idx, J * max_s * sizeof(int32_t)));
+  BM_TRY(dev_alloc(c, c->labels, J * max_s * sizeof(int32_t)));
+  BM_TRY(dev_alloc(c, c->Cp, J * max_k * cp * sizeof(float)));
+  BM_TRY(dev_alloc(c, c->cn, J * max_k * sizeof(float)));
+  BM_TRY(dev_alloc(c, c->Cinc, J * max_k * max_n * sizeof(float)));
+  BM_TRY(dev_alloc(c, c->deg_work, J * max_k));
+  BM_TRY(dev_alloc(c, c->deg_inc, J * max_k));
+  BM_TRY(dev_alloc(c, c->fhat, J * sizeof(double)));
+  BM_TRY(dev_alloc(c, c->acc, J * T * max_k * cp * sizeof(unsigned long long)));
+  BM_TRY(dev_alloc(c, c->cnt, J * T * max_k * sizeof(int32_t)));
+  const size_t tfn = std::max<size_t>(J * mc, (size_t)c->obj_chunks);
+  BM_TRY(dev_alloc(c, c->tf, tfn * sizeof(double)));
+  BM_TRY(dev_alloc(c, c->tnear, tfn * sizeof(int32_t)));
+  BM_TRY(dev_alloc(c, c->js, J * sizeof(JobState)));
+  BM_TRY(dev_alloc(c, c->counter, J * sizeof(int32_t)));
+  BM_TRY(dev_alloc(c, c->ndeg_acc, J * sizeof(int32_t)));
+  BM_TRY(dev_alloc(c, c->ntiles, J * sizeof(int32_t)));
+  BM_TRY(dev_alloc(c, c->sizes, J * sizeof(int64_t)));
+  const int64_t tcap = std::max<int64_t>((int64_t)J * T, c->tile_cap);
+  BM_TRY(dev_alloc(c, c->tile_job, tcap * sizeof(int32_t)));
+  BM_TRY(dev_alloc(c, c->tile_idx, tcap * sizeof(int32_t)));
+  c->tile_cap = tcap;
+  BM_TRY(dev_alloc(c, c->rkeys, J * 4 * sizeof(uint64_t)));
+  BM_TRY(dev_alloc(c, c->seed_worker, J * 2 * sizeof(uint64_t)));
+  BM_TRY(dev_alloc(c, c->absmax, (size_t)std::max(max_n, 1) * sizeof(unsigned int)));
+  BM_TRY(dev_alloc(c, c->scale, (size_t)cp * sizeof(double)));
+  BM_TRY(dev_alloc(c, c->inv_scale, (size_t)cp * sizeof(double)));
+  BM_TRY(dev_alloc(c, c->fjob, J * sizeof(double)));
+  BM_TRY(dev_alloc(c, c->nearjob, J * sizeof(long long)));
+  BM_TRY(dev_alloc(c, c->status, J * 4 * sizeof(int32_t)));
+  BM_TRY(dev_alloc(c, c->D, 4 * J * max_s * sizeof(float)));
+  BM_TRY(dev_alloc(c, c->Dt, 4 * J * mc * sizeof(double)));
+  BM_TRY(dev_alloc(c, c->ks, J * sizeof(KppState)));
+  BM_TRY(dev_alloc(c, c->todo, J * max_k * sizeof(int32_t)));
+  BM_TRY(dev_alloc(c, c->picks, J * max_k * 4 * sizeof(int32_t)));
+  c->max_s = max_s;
+  c->max_n = max_n;
+  c->max_k = max_k;
+  c->max_jobs = max_jobs;
+  c->cpmax = cp;
+  c->max_chunks = mc;
+  return BM_OK;
+}
+
+int ensure(bm_ctx* c, int64_t s, int n, int k, int jobs) {
+  if (s <= c->max_s && n <= c->max_n && k <= c->max_k && jobs <= c->max_jobs && c->S.p)
+    return BM_OK;
+  return reserve_impl(c, s, n, k, jobs);
+}
+
+int ensure_objective(bm_ctx* c, int64_t m) {
+  const int64_t ch = (m + bm::kWG - 1) / bm::kWG;
+  if (ch > (int64_t)(c->tf.bytes / sizeof(double))) {
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    BM_TRY(dev_alloc(c, c->tf, (size_t)ch * sizeof(double)));
+    BM_TRY(dev_alloc(c, c->tnear, (size_t)ch * sizeof(int32_t)));
+    c->obj_chunks = ch;
+  }
+  return BM_OK;
+}
+
+// Points per assignment workgroup: enough workgroups to fill the chip
+// (about 8 per compute unit over the whole batch).  Lloyd batches keep at
+// most kMaxTiles workgroups per job (the bound of the partial-sum buffers).
+int choose_tile_pts(const std::vector<int64_t>& sizes, bool bounded) {
+  int64_t total = 0, smax = 1;
+  for (int64_t s : sizes) {
+    total += s;
+    smax = std::max(smax, s);
+  }
+  const int64_t target = 2048;
+  int64_t chunks = (total + bm::kWG * target - 1) / (bm::kWG * target);
+  chunks = std::max<int64_t>(chunks, 1);
+  if (bounded) {
+    const int64_t per = (int64_t)bm::kWG * bm::kMaxTiles;
+    chunks = std::max(chunks, (smax + per - 1) / per);
+  }
+  return (int)(chunks * bm::kWG);
+}
+
+struct TileMap {
+  int tile_pts = bm::kWG;
+  int total = 0;
+  std::vector<int32_t> ntiles, job, idx;
+};
+
+TileMap make_tiles(const std::vector<int64_t>& sizes, int tile_pts) {
+  TileMap t;
+  t.tile_pts = tile_pts;
+  for (size_t j = 0; j < sizes.size(); ++j) {
+    const int nt = (int)((sizes[j] + tile_pts - 1) / tile_pts);
+    t.ntiles.push_back(nt);
+    for (int q = 0; q < nt; ++q) {
+      t.job.push_back((int32_t)j);
+      t.idx.push_back(q);
+    }
+  }
+  t.total = (int)t.job.size();
+  return t;
+}
+
+int upload_tiles(bm_ctx* c, const TileMap& t) {
+  if ((int64_t)t.total > c->tile_cap) {
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    BM_TRY(dev_alloc(c, c->tile_job, (size_t)t.total * sizeof(int32_t)));
+    BM_TRY(dev_alloc(c, c->tile_idx, (size_t)t.total * sizeof(int32_t)));
+    c->tile_cap = t.total;
+  }
+  const size_t chunk = kStageBytes / sizeof(int32_t);
+  for (size_t off = 0; off < (size_t)t.total; off += chunk) {
+    const size_t cntv = std::min(chunk, (size_t)t.total - off);
+    BM_TRY(upload(c, P<int32_t>(c->tile_job) + off, t.job.data() + off, cntv * sizeof(int32_t)));
+    BM_TRY(upload(c, P<int32_t>(c->tile_idx) + off, t.idx.data() + off, cntv * sizeof(int32_t)));
+  }
+  return BM_OK;
+}
+
+// Fixed-point scales from the data (max |x_d| over rows x n at stride ld).
+int compute_scales(bm_ctx* c, const float* X, int64_t rows, int n, int ld, int cp, int64_t max_s) {
+  HIP_TRY(c, hipMemsetAsync(c->absmax.p, 0, (size_t)n * sizeof(unsigned int), c->stream));
+  HIP_TRY(c, bm::launch_absmax(c->stream, X, rows, n, ld, P<unsigned int>(c->absmax)));
+  HIP_TRY(c, bm::launch_scales(c->stream, P<unsigned int>(c->absmax), n, cp, max_s,
+                               P<double>(c->scale), P<double>(c->inv_scale)));
+  return BM_OK;
+}
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+// A batch of jobs with shared n and k.  Job j's sample, centroids and
+// per-job state live at the job-j offsets of the workspace arrays, shifted
+// by `first` (so one worker can run alone in the plain path).
+struct BatchView {
+  int first = 0;     // first workspace job slot
+  int njobs = 0;
+  int n = 0, cp = 0, k = 0;
+  const float* S = nullptr;  // sample of slot `first`
+  int64_t S_stride = 0;      // floats between jobs (0: shared sample)
+  int ld = 0;
+  std::vector<int64_t> sizes;
+};
+
+// Run Lloyd on every job of the batch from the centroids in Cp (slots
+// first..first+njobs-1).  Leaves the final centroids in Cp, the job states in
+// js, degenerate flags in deg_work and optionally labels.
+int lloyd_batch(bm_ctx* c, const BatchView& b, int max_iter, double tol, int32_t* labels,
+                int64_t lab_stride) {
+  const int J = b.njobs, first = b.first, k = b.k, cp = b.cp;
+  TileMap tm = make_tiles(b.sizes, choose_tile_pts(b.sizes, true));
+  BM_TRY(upload_tiles(c, tm));
+  BM_TRY(upload(c, P<int32_t>(c->ntiles) + first, tm.ntiles.data(), J * sizeof(int32_t)));
+  BM_TRY(upload(c, P<int64_t>(c->sizes) + first, b.sizes.data(), J * sizeof(int64_t)));
+  JobState* js = P<JobState>(c->js) + first;
+  HIP_TRY(c, bm::launch_job_init(c->stream, js, P<int32_t>(c->ntiles) + first,
+                                 P<int64_t>(c->sizes) + first, J, P<int32_t>(c->counter) + first,
+                                 P<int32_t>(c->ndeg_acc) + first));
+  HIP_TRY(c, bm::launch_centroid_norms(c->stream, P<float>(c->Cp) + (int64_t)first * k * cp, cp, k,
+                                       J, P<float>(c->cn) + (int64_t)first * k));
+  bm::AssignArgs a{};
+  a.S = b.S;
+  a.S_stride = b.S_stride;
+  a.ld = b.ld;
+  a.n = b.n;
+  a.cp = cp;
+  a.k = k;
+  a.tile_pts = tm.tile_pts;
+  a.max_tiles = bm::kMaxTiles;
+  a.max_chunks = (int32_t)c->max_chunks;
+  a.vec = (b.ld == cp && aligned16(b.S) && (b.S_stride % 4) == 0) ? 1 : 0;
+  a.s = P<int64_t>(c->sizes) + first;
+  a.tile_job = P<int32_t>(c->tile_job);
+  a.tile_idx = P<int32_t>(c->tile_idx);
+  a.Cp = P<float>(c->Cp) + (int64_t)first * k * cp;
+  a.C_stride = (int64_t)k * cp;
+  a.cn = P<float>(c->cn) + (int64_t)first * k;
+  a.cn_stride = k;
+  a.labels = labels;
+  a.lab_stride = lab_stride;
+  a.tf = P<double>(c->tf) + (int64_t)first * c->max_chunks;
+  a.tnear = nullptr;
+  a.acc = P<unsigned long long>(c->acc) + (int64_t)first * bm::kMaxTiles * k * cp;
+  a.cnt = P<int32_t>(c->cnt) + (int64_t)first * bm::kMaxTiles * k;
+  a.scale = P<double>(c->scale);
+  a.st = js;
+
+  bm::FinalizeArgs f{};
+  f.n = b.n;
+  f.cp = cp;
+  f.k = k;
+  f.max_tiles = bm::kMaxTiles;
+  f.max_chunks = (int32_t)c->max_chunks;
+  f.max_iter = max_iter;
+  f.kc = std::max(1, bm::kWG / cp);
+  f.nchunks = (k + f.kc - 1) / f.kc;
+  f.tol = tol;
+  f.acc = a.acc;
+  f.cnt = a.cnt;
+  f.tf = a.tf;
+  f.inv_scale = P<double>(c->inv_scale);
+  f.Cp = P<float>(c->Cp) + (int64_t)first * k * cp;
+  f.cn = P<float>(c->cn) + (int64_t)first * k;
+  f.st = js;
+  f.deg = P<uint8_t>(c->deg_work) + (int64_t)first * k;
+  f.counter = P<int32_t>(c->counter) + first;
+  f.ndeg_acc = P<int32_t>(c->ndeg_acc) + first;
+
+  // Each job makes at most max_iter + 1 assignments.  Launch a few
+  // iterations between checks of the job states.
+  std::vector<JobState> hs(J);
+  int launched = 0;
+  int chunk = 3;
+  while (true) {
+    const int todo = std::min(chunk, max_iter + 1 - launched);
+    for (int q = 0; q < todo; ++q) {
+      HIP_TRY(c, bm::launch_assign(c->stream, a, tm.total, true));
+      HIP_TRY(c, bm::launch_finalize(c->stream, f, J));
+    }
+    launched += todo;
+    BM_TRY(readback(c, js, J * sizeof(JobState), hs.data()));
+    bool any = false;
+    for (int j = 0; j < J; ++j) any = any || hs[j].active;
+    if (!any) break;
+    if (launched >= max_iter + 1) return c->fail(BM_E_STATE, "Lloyd did not stop after %d steps", launched);
+    chunk = std::min(chunk * 2, 16);
+  }
+  return BM_OK;
+}
+
+// Objective of each job of the batch (no centroid update): fjob[first + j].
+int objective_batch(bm_ctx* c, const BatchView& b, int32_t* labels, int64_t lab_stride,
+                    int64_t max_chunks, bool near) {
+  const int J = b.njobs, first = b.first, k = b.k, cp = b.cp;
+  TileMap tm = make_tiles(b.sizes, choose_tile_pts(b.sizes, false));
+  BM_TRY(upload_tiles(c, tm));
+  BM_TRY(upload(c, P<int64_t>(c->sizes) + first, b.sizes.data(), J * sizeof(int64_t)));
+  bm::AssignArgs a{};
+  a.S = b.S;
+  a.S_stride = b.S_stride;
+  a.ld = b.ld;
+  a.n = b.n;
+  a.cp = cp;
+  a.k = k;
+  a.tile_pts = tm.tile_pts;
+  a.max_tiles = bm::kMaxTiles;
+  a.max_chunks = (int32_t)max_chunks;
+  a.vec = (b.ld == cp && aligned16(b.S) && (b.S_stride % 4) == 0) ? 1 : 0;
+  a.s = P<int64_t>(c->sizes) + first;
+  a.tile_job = P<int32_t>(c->tile_job);
+  a.tile_idx = P<int32_t>(c->tile_idx);
+  a.Cp = P<float>(c->Cp) + (int64_t)first * k * cp;
+  a.C_stride = (int64_t)k * cp;
+  a.cn = P<float>(c->cn) + (int64_t)first * k;
+  a.cn_stride = k;
+  a.labels = labels;
+  a.lab_stride = lab_stride;
+  a.tf = P<double>(c->tf);
+  a.tnear = near ? P<int32_t>(c->tnear) : nullptr;
+  a.acc = nullptr;
+  a.cnt = nullptr;
+  a.scale = nullptr;
+  a.st = nullptr;
+  HIP_TRY(c, bm::launch_assign(c->stream, a, tm.total, false));
+  HIP_TRY(c, bm::launch_reduce_f(c->stream, P<double>(c->tf), a.tnear,
+                                 P<int64_t>(c->sizes) + first, (int32_t)max_chunks, J,
+                                 P<double>(c->fjob) + first,
+                                 near ? P<long long>(c->nearjob) + first : nullptr));
+  return BM_OK;
+}
+
+struct KppBatch {
+  const uint64_t* seed_worker_host;  // [J][2]
+  uint64_t g;
+  int n_cand;
+  int steps;  // number of steps to run (max degenerate count over jobs)
+  int32_t* picks;
+};
+
+// Greedy K-means++ for the degenerate centroids of every job (Cp, deg_work).
+int kpp_batch(bm_ctx* c, const BatchView& b, const KppBatch& kb) {
+  const int J = b.njobs, first = b.first, k = b.k, cp = b.cp;
+  if (kb.steps <= 0) return BM_OK;
+  BM_TRY(upload(c, P<int64_t>(c->sizes) + first, b.sizes.data(), J * sizeof(int64_t)));
+  BM_TRY(upload(c, P<uint64_t>(c->seed_worker) + 2 * first, kb.seed_worker_host,
+                J * 2 * sizeof(uint64_t)));
+  int64_t smax = 0;
+  for (int64_t s : b.sizes) smax = std::max(smax, s);
+  bm::KppArgs a{};
+  a.S = b.S;
+  a.S_stride = b.S_stride;
+  a.ld = b.ld;
+  a.n = b.n;
+  a.cp = cp;
+  a.k = k;
+  a.ndt_max = (int32_t)c->max_chunks;
+  a.njobs = c->max_jobs;
+  a.s = P<int64_t>(c->sizes) + first;
+  a.Cp = P<float>(c->Cp) + (int64_t)first * k * cp;
+  a.C_stride = (int64_t)k * cp;
+  a.deg = P<uint8_t>(c->deg_work) + (int64_t)first * k;
+  a.D = P<float>(c->D) + (int64_t)first * c->max_s;
+  a.D_slot_stride = (int64_t)c->max_jobs * c->max_s;
+  a.D_job_stride = c->max_s;
+  a.Dt = P<double>(c->Dt) + (int64_t)first * c->max_chunks;
+  a.ks = P<KppState>(c->ks) + first;
+  a.todo = P<int32_t>(c->todo) + (int64_t)first * k;
+  a.picks = kb.picks;
+  a.seed_worker = P<uint64_t>(c->seed_worker) + 2 * first;
+  a.g = kb.g;
+  a.n_cand = kb.n_cand;
+  HIP_TRY(c, bm::launch_kpp_setup(c->stream, a, J));
+  HIP_TRY(c, bm::launch_kpp_init(c->stream, a, J, smax));
+  for (int step = 0; step < kb.steps; ++step) {
+    HIP_TRY(c, bm::launch_kpp_step(c->stream, a, J));
+    HIP_TRY(c, bm::launch_kpp_pot(c->stream, a, J, smax));
+  }
+  HIP_TRY(c, bm::launch_kpp_step(c->stream, a, J));  // commits the last step
+  return BM_OK;
+}
+
+int check_prec(bm_ctx* c, int prec) {
+  if (prec != BM_FP32) return c->fail(BM_E_ARG, "precision %d is not available (BM_FP32 only)", prec);
+  return BM_OK;
+}
+
+int check_dim(bm_ctx* c, int n) {
+  if (n < 1) return c->fail(BM_E_ARG, "n must be >= 1");
+  if (round_up4(n) > bm::kMaxRegDim)
+    return c->fail(BM_E_ARG, "n = %d exceeds the supported dimension %d", n, bm::kMaxRegDim);
+  return BM_OK;
+}
+
+uint64_t philox_word(uint64_t seed, uint32_t worker, uint32_t purpose, uint64_t c0, int word) {
+  uint64_t k0, k1;
+  bm::stream_key(seed, worker, purpose, &k0, &k1);
+  return bm::philox_ctr(c0, 0, 0, 0, k0, k1).w[word];
+}
+
+void round_keys(uint64_t m, uint64_t seed, uint32_t worker, uint32_t purpose, uint64_t g,
+                uint64_t out[4]) {
+  const bm::FeistelKey fk = bm::feistel_key(m, seed, worker, purpose, g);
+  for (int r = 0; r < 4; ++r) out[r] = fk.rk[r];
+}
+
+// Sample-size draw of Algorithm 1 under the configured policy.
+int64_t draw_size(const bm_params& p, uint32_t worker, int t, const int64_t* bacc,
+                  const int64_t* bpass, int32_t* bin) {
+  uint64_t k0, k1;
+  bm::stream_key(p.seed, worker, BM_PURPOSE_SIZE, &k0, &k1);
+  const bm::U64x4 w = bm::philox_ctr((uint64_t)t, 0, 0, 0, k0, k1);
+  const int64_t a = p.s_min, b = p.s_max;
+  *bin = 0;
+  if (p.size_policy == BM_SIZE_UNIFORM) return a + (int64_t)bm::bounded(w.w[0], (uint64_t)(b - a + 1));
+  if (p.size_policy == BM_SIZE_FIXED) return a;
+  const double la = std::log((double)a);
+  const double width = std::log((double)(b + 1)) - la;
+  if (p.size_policy == BM_SIZE_LOGUNIFORM || t == 0) {
+    const double u = bm::u01(w.w[0]);
+    int64_t s = (int64_t)std::floor(std::exp(la + u * width));
+    *bin = std::min(kNBins - 1, (int)(u * kNBins));
+    return std::min(std::max(s, a), b);
+  }
+  // BINS
+  double weights[kNBins];
+  double total = 0.0;
+  for (int i = 0; i < kNBins; ++i) {
+    weights[i] = ((double)bacc[i] + 1.0) / ((double)bpass[i] + 2.0);
+  }
+  for (int i = 0; i < kNBins; ++i) total += weights[i];  // in bin order
+  const double x = bm::u01(w.w[1]) * total;
+  double accw = 0.0;
+  int ib = kNBins - 1;
+  for (int i = 0; i < kNBins; ++i) {
+    accw += weights[i];
+    if (x < accw) {
+      ib = i;
+      break;
+    }
+  }
+  *bin = ib;
+  const double v = la + ((double)ib + bm::u01(w.w[2])) * (width / kNBins);
+  const int64_t s = (int64_t)std::floor(std::exp(v));
+  return std::min(std::max(s, a), b);
+}
+
+int validate_params(bm_ctx* c, const bm_params* p) {
+  if (!p) return c->fail(BM_E_ARG, "params is NULL");
+  if (p->m < 1 || p->m >= (1ll << 31)) return c->fail(BM_E_ARG, "m must be in [1, 2^31)");
+  if (p->k < 1 || p->k > p->s_min || p->s_min > p->s_max || p->s_max > p->m)
+    return c->fail(BM_E_ARG, "need 1 <= k <= s_min <= s_max <= m");
+  if (p->workers < 1 || p->rounds_T < 0 || p->passes_p < 1)
+    return c->fail(BM_E_ARG, "need workers >= 1, rounds_T >= 0, passes_p >= 1");
+  if (p->max_iter < 0 || !(p->tol >= 0.0)) return c->fail(BM_E_ARG, "need max_iter >= 0, tol >= 0");
+  if (p->n_candidates < 1 || p->n_candidates > 3) return c->fail(BM_E_ARG, "n_candidates in 1..3");
+  if (p->size_policy < 0 || p->size_policy > 3) return c->fail(BM_E_ARG, "unknown size policy");
+  if (p->size_policy == BM_SIZE_FIXED && p->s_min != p->s_max)
+    return c->fail(BM_E_ARG, "FIXED size policy needs s_min == s_max");
+  BM_TRY(check_prec(c, p->prec));
+  BM_TRY(check_dim(c, p->n));
+  return BM_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+BM_API int bm_version(void) { return BM_VERSION; }
+
+BM_API int bm_create(int device, void* hip_stream, bm_ctx** out) {
+  if (!out) return BM_E_ARG;
+  *out = nullptr;
+  bm_ctx* c = new (std::nothrow) bm_ctx();
+  if (!c) return BM_E_NOMEM;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+    delete c;
+    return BM_E_STATE;
+  }
+  if (hipSetDevice(device) != hipSuccess) {
+    delete c;
+    return BM_E_STATE;
+  }
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  bool ok = true;
+  for (int i = 0; i < kNumStage && ok; ++i) {
+    ok = hipHostMalloc(&c->stage[i], kStageBytes, hipHostMallocDefault) == hipSuccess &&
+         hipEventCreateWithFlags(&c->stage_ev[i], hipEventDisableTiming) == hipSuccess;
+  }
+  ok = ok && hipEventCreate(&c->ev0) == hipSuccess && hipEventCreate(&c->ev1) == hipSuccess &&
+       hipEventCreate(&c->ev2) == hipSuccess;
+  if (!ok) {
+    bm_destroy(c);
+    return BM_E_NOMEM;
+  }
+  *out = c;
+  return BM_OK;
+}
+
+BM_API void bm_destroy(bm_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  DevBuf* bufs[] = {&c->S,        &c->idx,     &c->labels,   &c->Cp,        &c->cn,
+                    &c->Cinc,     &c->deg_work, &c->deg_inc, &c->fhat,      &c->acc,
+                    &c->cnt,      &c->tf,      &c->tnear,    &c->js,        &c->counter,
+                    &c->ndeg_acc, &c->ntiles,  &c->sizes,    &c->tile_job,  &c->tile_idx,
+                    &c->rkeys,    &c->seed_worker, &c->absmax, &c->scale,   &c->inv_scale,
+                    &c->fjob,     &c->nearjob, &c->status,   &c->D,         &c->Dt,
+                    &c->ks,       &c->todo,    &c->picks};
+  for (DevBuf* b : bufs) dev_free(*b);
+  for (int i = 0; i < kNumStage; ++i) {
+    if (c->stage[i]) (void)hipHostFree(c->stage[i]);
+    if (c->stage_ev[i]) (void)hipEventDestroy(c->stage_ev[i]);
+  }
+  if (c->rb) (void)hipHostFree(c->rb);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  if (c->ev2) (void)hipEventDestroy(c->ev2);
+  delete c;
+}
+
+BM_API const char* bm_strerror(const bm_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+BM_API int bm_reserve(bm_ctx* c, int64_t max_s, int32_t max_n, int32_t max_k, int32_t max_jobs) {
+  if (!c) return BM_E_ARG;
+  if (max_s < 1 || max_n < 1 || max_k < 1 || max_jobs < 1)
+    return c->fail(BM_E_ARG, "reserve sizes must be >= 1");
+  HIP_TRY(c, hipSetDevice(c->device));
+  return reserve_impl(c, max_s, max_n, max_k, max_jobs);
+}
+
+BM_API int bm_sample(bm_ctx* c, const float* X, int64_t m, int32_t n, int64_t s, uint64_t seed,
+                     uint32_t worker, uint32_t purpose, uint64_t g, int32_t* idx_out,
+                     float* S_out) {
+  if (!c) return BM_E_ARG;
+  if (!X || !idx_out) return c->fail(BM_E_ARG, "X and idx_out are required");
+  if (n < 1 || s < 1 || s > m || m >= (1ll << 31)) return c->fail(BM_E_ARG, "need 1 <= s <= m < 2^31, n >= 1");
+  HIP_TRY(c, hipSetDevice(c->device));
+  BM_TRY(ensure(c, 1, 1, 1, 1));
+  uint64_t rk[4];
+  round_keys((uint64_t)m, seed, worker, purpose, g, rk);
+  BM_TRY(upload(c, P<int64_t>(c->sizes), &s, sizeof(int64_t)));
+  BM_TRY(upload(c, P<uint64_t>(c->rkeys), rk, sizeof rk));
+  HIP_TRY(c, bm::launch_sample(c->stream, X, m, n, 1, s, P<int64_t>(c->sizes), P<uint64_t>(c->rkeys),
+                               idx_out, 0, S_out, 0, n));
+  return BM_OK;
+}
+
+BM_API int bm_seed(bm_ctx* c, const float* S, int64_t s, int32_t n, int32_t k, float* C,
+                   uint8_t* degenerate, int32_t n_candidates, uint64_t seed, uint32_t worker,
+                   uint64_t g, int32_t* picks_out) {
+  if (!c) return BM_E_ARG;
+  if (!S || !C || !degenerate) return c->fail(BM_E_ARG, "S, C and degenerate are required");
+  if (k < 1 || s < k || n < 1) return c->fail(BM_E_ARG, "need 1 <= k <= s, n >= 1");
+  if (n_candidates < 1 || n_candidates > 3) return c->fail(BM_E_ARG, "n_candidates must be 1..3");
+  BM_TRY(check_dim(c, n));
+  HIP_TRY(c, hipSetDevice(c->device));
+  BM_TRY(ensure(c, s, n, k, 1));
+  const int cp = round_up4(n);
+  HIP_TRY(c, bm::launch_pad_centroids(c->stream, C, 0, n, cp, k, 1, P<float>(c->Cp), 0,
+                                      P<float>(c->cn), 0));
+  HIP_TRY(c, hipMemcpyAsync(c->deg_work.p, degenerate, (size_t)k, hipMemcpyDeviceToDevice, c->stream));
+  BatchView b;
+  b.first = 0;
+  b.njobs = 1;
+  b.n = n;
+  b.cp = cp;
+  b.k = k;
+  b.S = S;
+  b.S_stride = 0;
+  b.ld = n;
+  b.sizes = {s};
+  const uint64_t sw[2] = {seed, worker};
+  KppBatch kb{sw, g, n_candidates, k, picks_out};
+  BM_TRY(kpp_batch(c, b, kb));
+  HIP_TRY(c, bm::launch_unpad(c->stream, P<float>(c->Cp), cp, n, k, 1, C, 0));
+  HIP_TRY(c, hipMemcpyAsync(degenerate, c->deg_work.p, (size_t)k, hipMemcpyDeviceToDevice, c->stream));
+  return BM_OK;
+}
+
+BM_API int bm_lloyd(bm_ctx* c, const float* S, int64_t s, int32_t n, int32_t k, float* C,
+                    int32_t max_iter, double tol, int32_t prec, double* f_out, int32_t* iters_out,
+                    uint8_t* degenerate_out, int32_t* labels_out) {
+  if (!c) return BM_E_ARG;
+  if (!S || !C || !f_out) return c->fail(BM_E_ARG, "S, C and f_out are required");
+  if (k < 1 || s < 1 || max_iter < 0 || !(tol >= 0.0)) return c->fail(BM_E_ARG, "need k >= 1, s >= 1, max_iter >= 0, tol >= 0");
+  BM_TRY(check_prec(c, prec));
+  BM_TRY(check_dim(c, n));
+  HIP_TRY(c, hipSetDevice(c->device));
+  BM_TRY(ensure(c, s, n, k, 1));
+  const int cp = round_up4(n);
+  BM_TRY(compute_scales(c, S, s, n, n, cp, s));
+  HIP_TRY(c, bm::launch_pad_centroids(c->stream, C, 0, n, cp, k, 1, P<float>(c->Cp), 0,
+                                      P<float>(c->cn), 0));
+  BatchView b;
+  b.first = 0;
+  b.njobs = 1;
+  b.n = n;
+  b.cp = cp;
+  b.k = k;
+  b.S = S;
+  b.S_stride = 0;
+  b.ld = n;
+  b.sizes = {s};
+  BM_TRY(lloyd_batch(c, b, max_iter, tol, labels_out, 0));
+  HIP_TRY(c, bm::launch_unpad(c->stream, P<float>(c->Cp), cp, n, k, 1, C, 0));
+  if (degenerate_out)
+    HIP_TRY(c, hipMemcpyAsync(degenerate_out, c->deg_work.p, (size_t)k, hipMemcpyDeviceToDevice, c->stream));
+  JobState st;
+  BM_TRY(readback(c, c->js.p, sizeof(JobState), &st));
+  *f_out = st.f;
+  if (iters_out) *iters_out = st.iter;
+  if (!std::isfinite(st.f)) return c->fail(BM_E_NONFINITE, "objective is not finite");
+  return BM_OK;
+}
+
+BM_API int bm_objective(bm_ctx* c, const float* X, int64_t m, int32_t n, const float* C, int32_t k,
+                        int32_t prec, double* f_out, int32_t* labels_out, int64_t* near_ties_out) {
+  if (!c) return BM_E_ARG;
+  if (!X || !C || !f_out) return c->fail(BM_E_ARG, "X, C and f_out are required");
+  if (k < 1 || m < 1) return c->fail(BM_E_ARG, "need k >= 1, m >= 1");
+  BM_TRY(check_prec(c, prec));
+  BM_TRY(check_dim(c, n));
+  HIP_TRY(c, hipSetDevice(c->device));
+  BM_TRY(ensure(c, 1, n, k, 1));
+  BM_TRY(ensure_objective(c, m));
+  const int cp = round_up4(n);
+  HIP_TRY(c, bm::launch_pad_centroids(c->stream, C, 0, n, cp, k, 1, P<float>(c->Cp), 0,
+                                      P<float>(c->cn), 0));
+  BatchView b;
+  b.first = 0;
+  b.njobs = 1;
+  b.n = n;
+  b.cp = cp;
+  b.k = k;
+  b.S = X;
+  b.S_stride = 0;
+  b.ld = n;
+  b.sizes = {m};
+  BM_TRY(objective_batch(c, b, labels_out, 0, (m + bm::kWG - 1) / bm::kWG, near_ties_out != nullptr));
+  double f;
+  BM_TRY(readback(c, c->fjob.p, sizeof(double), &f));
+  *f_out = f;
+  if (near_ties_out) {
+    long long nn;
+    BM_TRY(readback(c, c->nearjob.p, sizeof(long long), &nn));
+    *near_ties_out = nn;
+  }
+  if (!std::isfinite(f)) return c->fail(BM_E_NONFINITE, "objective is not finite");
+  return BM_OK;
+}
+
+BM_API int bm_draw_size(const bm_params* params, uint32_t worker, int32_t t, const int64_t* bin_acc,
+                        const int64_t* bin_passes, int64_t* s_out, int32_t* bin_out) {
+  if (!params || !s_out || t < 0) return BM_E_ARG;
+  if (params->size_policy == BM_SIZE_BINS && t > 0 && (!bin_acc || !bin_passes)) return BM_E_ARG;
+  if (params->s_min < 1 || params->s_min > params->s_max) return BM_E_ARG;
+  int32_t bin = 0;
+  *s_out = draw_size(*params, worker, t, bin_acc, bin_passes, &bin);
+  if (bin_out) *bin_out = bin;
+  return BM_OK;
+}
+
+BM_API void bm_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
+  bm::U64x4 x;
+  for (int i = 0; i < 4; ++i) x.w[i] = ctr[i];
+  const bm::U64x4 y = bm::philox4x64_10(x, key[0], key[1]);
+  for (int i = 0; i < 4; ++i) out[i] = y.w[i];
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 1
+// ---------------------------------------------------------------------------
+BM_API int bm_bigmeans_run(bm_ctx* c, const float* X, const bm_params* params, float* C_best_out,
+                           int32_t* Y_out, bm_result* out, bm_trace_cb cb, void* user) {
+  if (!c) return BM_E_ARG;
+  BM_TRY(validate_params(c, params));
+  if (!X || !C_best_out || !out) return c->fail(BM_E_ARG, "X, C_best_out and out are required");
+  const bm_params p = *params;
+  const int W = p.workers, k = p.k, n = p.n, cp = round_up4(n);
+  const int64_t m = p.m;
+  HIP_TRY(c, hipSetDevice(c->device));
+  BM_TRY(ensure(c, p.s_max, n, k, W));
+  BM_TRY(ensure_objective(c, m));
+  hipStream_t st = c->stream;
+
+  HIP_TRY(c, hipEventRecord(c->ev0, st));
+  BM_TRY(compute_scales(c, X, m, n, n, cp, p.s_max));
+
+  // incumbents: all centroids degenerate, f_hat = +inf (Algorithm 1, initialisation)
+  HIP_TRY(c, hipMemsetAsync(c->Cinc.p, 0, (size_t)W * k * n * sizeof(float), st));
+  HIP_TRY(c, hipMemsetAsync(c->deg_inc.p, 1, (size_t)W * k, st));
+  std::vector<double> fhat(W, std::numeric_limits<double>::infinity());
+  BM_TRY(upload(c, c->fhat.p, fhat.data(), W * sizeof(double)));
+  std::vector<int64_t> s_cur(W, -1), s_new(W, 0);
+  std::vector<int32_t> bin_cur(W, 0);
+  std::vector<int32_t> ndeg(W, k);
+  int64_t bacc[kNBins] = {0}, bpass[kNBins] = {0};
+  int64_t Lsum = 0, Lcount = 0;
+  int64_t lloyd_dists = 0, lloyd_iters = 0;
+  double lloyd_ms = 0.0;
+  std::vector<uint64_t> sw(2 * (size_t)W);
+  for (int w = 0; w < W; ++w) {
+    sw[2 * w] = p.seed;
+    sw[2 * w + 1] = (uint64_t)w;
+  }
+  std::vector<uint64_t> rk(4 * (size_t)W);
+  std::vector<int32_t> status(4 * (size_t)W);
+  const int64_t Sj = c->max_s * cp;  // floats between job samples
+  float* Sbase = P<float>(c->S);
+
+  // The batch a pass runs on: all workers together, or one worker alone.
+  std::vector<std::pair<int, int>> groups;
+  if (p.batched)
+    groups.push_back({0, W});
+  else
+    for (int w = 0; w < W; ++w) groups.push_back({w, 1});
+
+  for (int t = 0; t < p.rounds_T; ++t) {
+    int64_t rpass[kNBins] = {0}, racc[kNBins] = {0};
+    for (int w = 0; w < W; ++w) s_new[w] = draw_size(p, (uint32_t)w, t, bacc, bpass, &bin_cur[w]);
+
+    // Re-evaluate incumbents whose sample size changed (Algorithm 1; Section 4.2).
+    std::vector<int> rec;
+    for (int w = 0; w < W; ++w)
+      if (std::isfinite(fhat[w]) && s_new[w] != s_cur[w]) rec.push_back(w);
+    if (!rec.empty()) {
+      // job slot = worker slot; run each recalc worker as its own group slot
+      for (size_t r = 0; r < rec.size(); ++r) {
+        const int w = rec[r];
+        round_keys((uint64_t)m, p.seed, (uint32_t)w, BM_PURPOSE_RECALC, (uint64_t)t, &rk[4 * w]);
+      }
+      BM_TRY(upload(c, P<uint64_t>(c->rkeys), rk.data(), 4 * W * sizeof(uint64_t)));
+      // one batch over all worker slots; slots not re-evaluated get size 0
+      std::vector<int64_t> szs(W, 0);
+      for (int w : rec) szs[w] = s_new[w];
+      BM_TRY(upload(c, P<int64_t>(c->sizes), szs.data(), W * sizeof(int64_t)));
+      HIP_TRY(c, bm::launch_sample(st, X, m, n, W, p.s_max, P<int64_t>(c->sizes),
+                                   P<uint64_t>(c->rkeys), P<int32_t>(c->idx), c->max_s, Sbase, Sj,
+                                   cp));
+      HIP_TRY(c, bm::launch_pad_centroids(st, P<float>(c->Cinc), (int64_t)k * n, n, cp, k, W,
+                                          P<float>(c->Cp), (int64_t)k * cp, P<float>(c->cn), k));
+      BatchView b;
+      b.first = 0;
+      b.njobs = W;
+      b.n = n;
+      b.cp = cp;
+      b.k = k;
+      b.S = Sbase;
+      b.S_stride = Sj;
+      b.ld = cp;
+      b.sizes = szs;  // zero-size jobs produce no tiles and f = 0
+      BM_TRY(objective_batch(c, b, nullptr, 0, c->max_chunks, false));
+      std::vector<double> fr(W);
+      BM_TRY(readback(c, c->fjob.p, W * sizeof(double), fr.data()));
+      for (int w : rec) fhat[w] = fr[w];
+      BM_TRY(upload(c, c->fhat.p, fhat.data(), W * sizeof(double)));
+    }
+    for (int w = 0; w < W; ++w) s_cur[w] = s_new[w];
+
+    for (int q = 0; q < p.passes_p; ++q) {
+      const uint64_t g = (uint64_t)t * p.passes_p + q;
+      for (int w = 0; w < W; ++w)
+        round_keys((uint64_t)m, p.seed, (uint32_t)w, BM_PURPOSE_SAMPLE, g, &rk[4 * w]);
+      BM_TRY(upload(c, P<uint64_t>(c->rkeys), rk.data(), 4 * W * sizeof(uint64_t)));
+      for (const auto& grp : groups) {
+        const int first = grp.first, J = grp.second;
+        std::vector<int64_t> szs(s_cur.begin() + first, s_cur.begin() + first + J);
+        int64_t smax = 0;
+        int steps = 0;
+        for (int j = 0; j < J; ++j) {
+          smax = std::max(smax, szs[j]);
+          steps = std::max(steps, ndeg[first + j]);
+        }
+        BM_TRY(upload(c, P<int64_t>(c->sizes) + first, szs.data(), J * sizeof(int64_t)));
+        // sample S_w (Algorithm 1)
+        HIP_TRY(c, bm::launch_sample(st, X, m, n, J, smax, P<int64_t>(c->sizes) + first,
+                                     P<uint64_t>(c->rkeys) + 4 * first,
+                                     P<int32_t>(c->idx) + (int64_t)first * c->max_s, c->max_s,
+                                     Sbase + (int64_t)first * Sj, Sj, cp));
+        HIP_TRY(c, bm::launch_copy_incumbent(st, P<float>(c->Cinc) + (int64_t)first * k * n,
+                                             P<uint8_t>(c->deg_inc) + (int64_t)first * k, n, cp, k,
+                                             J, P<float>(c->Cp) + (int64_t)first * k * cp,
+                                             P<float>(c->cn) + (int64_t)first * k,
+                                             P<uint8_t>(c->deg_work) + (int64_t)first * k));
+        BatchView b;
+        b.first = first;
+        b.njobs = J;
+        b.n = n;
+        b.cp = cp;
+        b.k = k;
+        b.S = Sbase + (int64_t)first * Sj;
+        b.S_stride = Sj;
+        b.ld = cp;
+        b.sizes = szs;
+        // K-means++ for degenerate centroids
+        KppBatch kb{sw.data() + 2 * first, g, p.n_candidates, steps, nullptr};
+        BM_TRY(kpp_batch(c, b, kb));
+        // Lloyd
+        HIP_TRY(c, hipEventRecord(c->ev1, st));
+        BM_TRY(lloyd_batch(c, b, p.max_iter, p.tol, nullptr, 0));
+        HIP_TRY(c, hipEventRecord(c->ev2, st));
+        // accept
+        HIP_TRY(c, bm::launch_accept(st, P<float>(c->Cp) + (int64_t)first * k * cp, cp, n, k, J,
+                                     P<JobState>(c->js) + first,
+                                     P<uint8_t>(c->deg_work) + (int64_t)first * k,
+                                     P<float>(c->Cinc) + (int64_t)first * k * n,
+                                     P<uint8_t>(c->deg_inc) + (int64_t)first * k,
+                                     P<double>(c->fhat) + first, P<int32_t>(c->status) + 4 * first));
+        BM_TRY(readback(c, P<int32_t>(c->status) + 4 * first, 4 * J * sizeof(int32_t),
+                        status.data() + 4 * first));
+        BM_TRY(readback(c, P<double>(c->fhat) + first, J * sizeof(double), fhat.data() + first));
+        float ms = 0.f;
+        HIP_TRY(c, hipEventElapsedTime(&ms, c->ev1, c->ev2));
+        lloyd_ms += ms;
+        for (int j = 0; j < J; ++j) {
+          const int w = first + j;
+          const int32_t* sw4 = &status[4 * w];
+          lloyd_iters += sw4[1] + 1;
+          lloyd_dists += (int64_t)(sw4[1] + 1) * s_cur[w] * k;
+          ndeg[w] = sw4[2];
+          rpass[bin_cur[w]] += 1;
+          if (sw4[0]) {
+            Lsum += s_cur[w];
+            Lcount += 1;
+            racc[bin_cur[w]] += 1;
+          }
+        }
+      }
+    }
+    for (int i = 0; i < kNBins; ++i) {
+      bacc[i] += racc[i];
+      bpass[i] += rpass[i];
+    }
+    if (cb) {
+      HIP_TRY(c, hipEventRecord(c->ev1, st));
+      HIP_TRY(c, hipEventSynchronize(c->ev1));
+      float ms = 0.f;
+      HIP_TRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+      cb(user, t, P<float>(c->Cinc), fhat.data(), s_cur.data(), ms * 1e-3);
+    }
+  }
+
+  // s_opt: round-half-up mean of L (Algorithm 1; Section 4.2 "simple mean")
+  const int64_t s_opt = Lcount > 0 ? (Lsum + Lcount / 2) / Lcount : p.s_max;
+  // one shared sample of size s_opt; every incumbent scored on it
+  round_keys((uint64_t)m, p.seed, BM_FINAL_WORKER, BM_PURPOSE_FINAL, 0, rk.data());
+  BM_TRY(upload(c, P<int64_t>(c->sizes), &s_opt, sizeof(int64_t)));
+  BM_TRY(upload(c, P<uint64_t>(c->rkeys), rk.data(), 4 * sizeof(uint64_t)));
+  HIP_TRY(c, bm::launch_sample(st, X, m, n, 1, s_opt, P<int64_t>(c->sizes), P<uint64_t>(c->rkeys),
+                               P<int32_t>(c->idx), c->max_s, Sbase, Sj, cp));
+  HIP_TRY(c, bm::launch_pad_centroids(st, P<float>(c->Cinc), (int64_t)k * n, n, cp, k, W,
+                                      P<float>(c->Cp), (int64_t)k * cp, P<float>(c->cn), k));
+  BatchView fb;
+  fb.first = 0;
+  fb.njobs = W;
+  fb.n = n;
+  fb.cp = cp;
+  fb.k = k;
+  fb.S = Sbase;
+  fb.S_stride = 0;  // shared sample
+  fb.ld = cp;
+  fb.sizes.assign(W, s_opt);
+  BM_TRY(objective_batch(c, fb, nullptr, 0, c->max_chunks, false));
+  std::vector<double> ffin(W);
+  BM_TRY(readback(c, c->fjob.p, W * sizeof(double), ffin.data()));
+  int best = -1;
+  for (int w = 0; w < W; ++w) {
+    if (!std::isfinite(fhat[w])) ffin[w] = std::numeric_limits<double>::infinity();
+    // smallest value, NaN last, lowest worker on ties
+    if (best < 0) {
+      best = w;
+      continue;
+    }
+    const bool nb = std::isnan(ffin[best]), nw = std::isnan(ffin[w]);
+    if ((nb && !nw) || (!nw && !nb && ffin[w] < ffin[best])) best = w;
+  }
+  // full assignment of X with C_best (Algorithm 1, last step)
+  HIP_TRY(c, hipMemcpyAsync(C_best_out, P<float>(c->Cinc) + (int64_t)best * k * n,
+                            (size_t)k * n * sizeof(float), hipMemcpyDeviceToDevice, st));
+  HIP_TRY(c, bm::launch_pad_centroids(st, C_best_out, 0, n, cp, k, 1, P<float>(c->Cp), 0,
+                                      P<float>(c->cn), 0));
+  BatchView xb;
+  xb.first = 0;
+  xb.njobs = 1;
+  xb.n = n;
+  xb.cp = cp;
+  xb.k = k;
+  xb.S = X;
+  xb.S_stride = 0;
+  xb.ld = n;
+  xb.sizes = {m};
+  BM_TRY(objective_batch(c, xb, Y_out, 0, (m + bm::kWG - 1) / bm::kWG, false));
+  double f_full;
+  BM_TRY(readback(c, c->fjob.p, sizeof(double), &f_full));
+  HIP_TRY(c, hipEventRecord(c->ev1, st));
+  HIP_TRY(c, hipEventSynchronize(c->ev1));
+  float total_ms = 0.f;
+  HIP_TRY(c, hipEventElapsedTime(&total_ms, c->ev0, c->ev1));
+
+  out->f_full = f_full;
+  out->f_best_sample = ffin[best];
+  out->s_opt = s_opt;
+  out->improvements = Lcount;
+  out->lloyd_dists = lloyd_dists;
+  out->lloyd_iters = lloyd_iters;
+  out->best_worker = best;
+  out->pad_ = 0;
+  out->gpu_seconds = total_ms * 1e-3;
+  out->lloyd_seconds = lloyd_ms * 1e-3;
+  if (!std::isfinite(f_full)) return c->fail(BM_E_NONFINITE, "f(C_best, X) is not finite");
+  return BM_OK;
+}
+
+}  // extern "C"

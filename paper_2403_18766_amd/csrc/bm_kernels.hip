@@ -1,0 +1,960 @@
+// gfx950 kernels of the Big-means hot path.
+//
+//   k_sample          sample without replacement + row gather (Section 4.1)
+//   k_assign_small    nearest-centre assignment, FP64 objective partials and
+//                     fixed-point per-cluster sums for one Lloyd iteration, or
+//                     the objective of Eq. (1) alone (dimension <= 64)
+//   k_finalize        cluster means, convergence test, Lloyd job state
+//   k_kpp_*           greedy K-means++ steps (Section 3, Section 5)
+//   k_accept          strict-improvement acceptance (Algorithm 1)
+//
+// Layout: samples are row-major with a padded row stride cp (a multiple of 4,
+// zero-filled), so a point is NP/4 16-byte loads and sits in NP registers of
+// its lane; centroids are padded the same way and are uniform across a wave,
+// so the compiler reads them with scalar loads (SGPR operands of the FMAs).
+//
+// Numerics: the argmin runs on e_j = ||c_j||^2 - 2 x.c_j (one FMA per
+// dimension).  Its rounding error is bounded per point by
+// B = 2(2 gamma + 2u)(|x| cmax + cmax^2), gamma = (NP/4+2)u/(1-(NP/4+2)u),
+// u = 2^-24 (four interleaved partial sums).  A point whose two best e
+// differ by more than 2B plus 2.5e-5 (e2 + |x|^2) keeps its winner; any other
+// point is decided again in the direct form sum_d (x_d - c_d)^2 over all
+// centres (lowest index on ties), which also counts the near ties
+// d2 - d1 < 1e-5 d2.  The winner's distance entering f is always the direct
+// form.  f is summed in FP64 in a fixed order (wave butterfly, waves, tiles),
+// and the per-cluster sums are exact 64-bit fixed-point integers, so every
+// result is bitwise reproducible and independent of scheduling.
+
+#include <math.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+#include "bm_internal.h"
+#include "bm_rng.h"
+
+namespace bm {
+
+namespace {
+
+constexpr float kU = 5.9604644775390625e-8f;  // 2^-24
+
+__device__ inline double wave_sum_f64(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ inline int wave_sum_i32(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Deterministic sum over a 256-thread workgroup; result valid in thread 0.
+__device__ inline double block_sum_f64(double v, double* sh4) {
+  v = wave_sum_f64(v);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sh4[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) r = (sh4[0] + sh4[1]) + (sh4[2] + sh4[3]);
+  __syncthreads();
+  return r;
+}
+
+__device__ inline int block_sum_i32(int v, int* sh4) {
+  v = wave_sum_i32(v);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sh4[w] = v;
+  __syncthreads();
+  int r = 0;
+  if (threadIdx.x == 0) r = (sh4[0] + sh4[1]) + (sh4[2] + sh4[3]);
+  __syncthreads();
+  return r;
+}
+
+// Deterministic sum of v[0..cnt) by one wave: lane l adds a contiguous chunk
+// in order, then the 64 chunk totals are added in lane order.  The result is
+// the same in every lane and depends only on cnt and the values.
+__device__ inline double wave_chunked_sum(const double* __restrict__ v, int64_t cnt) {
+  const int lane = threadIdx.x & 63;
+  const int64_t cs = (cnt + 63) / 64;
+  const int64_t lo = min(cnt, (int64_t)lane * cs), hi = min(cnt, lo + cs);
+  double tot = 0.0;
+  for (int64_t q = lo; q < hi; ++q) tot += v[q];
+  double total = 0.0;
+  for (int l = 0; l < 64; ++l) total += __shfl(tot, l, 64);
+  return total;
+}
+
+// min that propagates NaN from either operand.
+__device__ inline float min_nan(float a, float b) {
+  const float r = b < a ? b : a;
+  return (a != a || b != b) ? __builtin_nanf("") : r;
+}
+
+// Squared distance in the direct form with four interleaved partial sums;
+// x and c are read from memory (any n).
+__device__ inline float dist_direct_mem(const float* __restrict__ x, const float* __restrict__ c,
+                                        int n) {
+  float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
+  int d = 0;
+  for (; d + 4 <= n; d += 4) {
+    const float t0 = x[d] - c[d], t1 = x[d + 1] - c[d + 1];
+    const float t2 = x[d + 2] - c[d + 2], t3 = x[d + 3] - c[d + 3];
+    p0 = fmaf(t0, t0, p0);
+    p1 = fmaf(t1, t1, p1);
+    p2 = fmaf(t2, t2, p2);
+    p3 = fmaf(t3, t3, p3);
+  }
+  for (; d < n; ++d) {
+    const float t = x[d] - c[d];
+    p0 = fmaf(t, t, p0);
+  }
+  return (p0 + p1) + (p2 + p3);
+}
+
+template <int NP>
+__device__ inline float dist_direct_reg(const float (&x)[NP], const float* __restrict__ c) {
+  float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
+#pragma unroll
+  for (int d = 0; d < NP; d += 4) {
+    const float t0 = x[d] - c[d], t1 = x[d + 1] - c[d + 1];
+    const float t2 = x[d + 2] - c[d + 2], t3 = x[d + 3] - c[d + 3];
+    p0 = fmaf(t0, t0, p0);
+    p1 = fmaf(t1, t1, p1);
+    p2 = fmaf(t2, t2, p2);
+    p3 = fmaf(t3, t3, p3);
+  }
+  return (p0 + p1) + (p2 + p3);
+}
+
+template <int NP>
+__device__ inline float dot_reg(const float (&x)[NP], const float* __restrict__ c) {
+  float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
+#pragma unroll
+  for (int d = 0; d < NP; d += 4) {
+    p0 = fmaf(x[d], c[d], p0);
+    p1 = fmaf(x[d + 1], c[d + 1], p1);
+    p2 = fmaf(x[d + 2], c[d + 2], p2);
+    p3 = fmaf(x[d + 3], c[d + 3], p3);
+  }
+  return (p0 + p1) + (p2 + p3);
+}
+
+// ---------------------------------------------------------------------------
+// Sampling: grid (ceil(max_s / 256), jobs).  Phase 1: one Feistel index per
+// thread.  Phase 2: the workgroup copies its 256 rows with consecutive
+// threads on consecutive 16-byte pieces of a row.
+// ---------------------------------------------------------------------------
+template <bool VEC>
+__global__ __launch_bounds__(kWG) void k_sample(const float* __restrict__ X, int64_t m, int n,
+                                                 const int64_t* __restrict__ sizes,
+                                                 const uint64_t* __restrict__ rkeys,
+                                                 int32_t* __restrict__ idx, int64_t idx_stride,
+                                                 float* __restrict__ S, int64_t S_stride, int ld) {
+  const int job = blockIdx.y;
+  const int64_t sj = sizes[job];
+  const int64_t base = (int64_t)blockIdx.x * kWG;
+  if (base >= sj) return;
+  __shared__ int64_t rows[kWG];
+  FeistelKey fk;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) fk.rk[r] = rkeys[job * 4 + r];
+  fk.m = (uint64_t)m;
+  fk.h = feistel_half_bits((uint64_t)m);
+  const int64_t i = base + threadIdx.x;
+  if (i < sj) {
+    const uint64_t y = feistel_index((uint64_t)i, fk);
+    rows[threadIdx.x] = (int64_t)y;
+    if (idx) idx[job * idx_stride + i] = (int32_t)y;
+  }
+  __syncthreads();
+  if (S == nullptr) return;
+  const int nrows = (int)min((int64_t)kWG, sj - base);
+  float* __restrict__ Sj = S + job * S_stride + base * ld;
+  if (VEC) {
+    const int nv = n >> 2, lv = ld >> 2;
+    for (int e = threadIdx.x; e < nrows * lv; e += kWG) {
+      const int r = e / lv, c = e - r * lv;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (c < nv) v = reinterpret_cast<const float4*>(X + rows[r] * (int64_t)n)[c];
+      reinterpret_cast<float4*>(Sj + (int64_t)r * ld)[c] = v;
+    }
+  } else {
+    for (int e = threadIdx.x; e < nrows * ld; e += kWG) {
+      const int r = e / ld, c = e - r * ld;
+      Sj[(int64_t)r * ld + c] = c < n ? X[rows[r] * (int64_t)n + c] : 0.f;
+    }
+  }
+}
+
+// Per-dimension max |x| as float bits (non-negative floats order like uints).
+__global__ __launch_bounds__(kWG) void k_absmax(const float* __restrict__ X, int64_t rows, int n,
+                                                 int ld, unsigned int* __restrict__ out) {
+  extern __shared__ unsigned int smax[];
+  for (int d = threadIdx.x; d < n; d += kWG) smax[d] = 0u;
+  __syncthreads();
+  const int64_t total = rows * (int64_t)n;
+  for (int64_t e = (int64_t)blockIdx.x * kWG + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * kWG) {
+    const int64_t r = e / n;
+    const int d = (int)(e - r * n);
+    const unsigned int b = __float_as_uint(X[r * ld + d]) & 0x7fffffffu;
+    atomicMax(&smax[d], b);
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d < n; d += kWG) atomicMax(&out[d], smax[d]);
+}
+
+// Fixed-point scales: every |x_d| < 2^e_d, so each of at most 2^L points
+// contributes less than 2^(62-L) in magnitude and a cluster sum stays below
+// 2^62: scale_d = 2^(62 - e_d - L).
+__global__ void k_scales(const unsigned int* __restrict__ absmax_bits, int n, int cp,
+                         int64_t max_s, double* __restrict__ scale,
+                         double* __restrict__ inv_scale) {
+  const int d = threadIdx.x + blockIdx.x * blockDim.x;
+  if (d >= cp) return;
+  int L = 0;
+  while (L < 62 && (1ll << L) < max_s) ++L;
+  int shift = 62 - L;
+  if (d < n) {
+    const float a = __uint_as_float(absmax_bits[d]);
+    if (a > 0.f && a <= 3.4028234663852886e38f) {
+      int e;
+      frexp((double)a, &e);  // a = f 2^e, f in [0.5, 1): a < 2^e
+      shift = 62 - e - L;
+    }
+  }
+  scale[d] = ldexp(1.0, shift);
+  inv_scale[d] = ldexp(1.0, -shift);
+}
+
+// Pad k x n centroids into k x cp rows (zero fill) and compute ||c||^2 in FP64.
+__global__ __launch_bounds__(kWG) void k_pad_centroids(const float* __restrict__ C,
+                                                        int64_t C_stride, int n, int cp, int k,
+                                                        float* __restrict__ Cp,
+                                                        int64_t Cp_stride,
+                                                        float* __restrict__ cn,
+                                                        int64_t cn_stride) {
+  const int job = blockIdx.x;
+  const float* Cj = C + job * C_stride;
+  float* Cpj = Cp + job * Cp_stride;
+  for (int e = threadIdx.x; e < k * cp; e += kWG) {
+    const int r = e / cp, d = e - r * cp;
+    Cpj[e] = d < n ? Cj[(int64_t)r * n + d] : 0.f;
+  }
+  for (int r = threadIdx.x; r < k; r += kWG) {
+    double acc = 0.0;
+    for (int d = 0; d < n; ++d) {
+      const double v = Cj[(int64_t)r * n + d];
+      acc += v * v;
+    }
+    cn[job * cn_stride + r] = (float)acc;
+  }
+}
+
+__global__ __launch_bounds__(kWG) void k_centroid_norms(const float* __restrict__ Cp, int cp,
+                                                         int k, float* __restrict__ cn) {
+  const int job = blockIdx.x;
+  for (int r = threadIdx.x; r < k; r += kWG) {
+    const float* c = Cp + ((int64_t)job * k + r) * cp;
+    double acc = 0.0;
+    for (int d = 0; d < cp; ++d) acc += (double)c[d] * (double)c[d];
+    cn[(int64_t)job * k + r] = (float)acc;
+  }
+}
+
+__global__ __launch_bounds__(kWG) void k_unpad(const float* __restrict__ Cp, int cp, int n, int k,
+                                               float* __restrict__ C, int64_t C_stride) {
+  const int job = blockIdx.x;
+  for (int e = threadIdx.x; e < k * n; e += kWG) {
+    const int r = e / n, d = e - r * n;
+    C[job * C_stride + e] = Cp[((int64_t)job * k + r) * cp + d];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Assignment.  Grid = flattened tiles of all jobs; each workgroup handles
+// tile_pts points of one job in chunks of 256 (one point per lane).
+// ---------------------------------------------------------------------------
+template <int NP, bool SUMS>
+__global__ __launch_bounds__(kWG) void k_assign_small(AssignArgs a) {
+  const int job = a.tile_job[blockIdx.x];
+  const int t = a.tile_idx[blockIdx.x];
+  if (a.st && !a.st[job].active) return;
+  const int64_t s = a.s[job];
+  const int64_t p_begin = (int64_t)t * a.tile_pts;
+  const int64_t p_end = min(s, p_begin + a.tile_pts);
+  const float* __restrict__ S = a.S + job * a.S_stride;
+  const float* __restrict__ C = a.Cp + job * a.C_stride;
+  const float* __restrict__ cn = a.cn + job * a.cn_stride;
+  const int k = a.k;
+  const int n = a.n;
+  const int ld = a.ld;
+
+  extern __shared__ unsigned long long lds_acc[];  // SUMS: [k][NP] sums, then [k] counts
+  unsigned int* lds_cnt = reinterpret_cast<unsigned int*>(lds_acc + (SUMS ? k * NP : 0));
+  __shared__ double red_f[4];
+  __shared__ int red_i[4];
+
+  if (SUMS) {
+    for (int e = threadIdx.x; e < k * NP; e += kWG) lds_acc[e] = 0ull;
+    for (int e = threadIdx.x; e < k; e += kWG) lds_cnt[e] = 0u;
+    __syncthreads();
+  }
+
+  float cmax2 = 0.f;
+  for (int j = 0; j < k; ++j) cmax2 = fmaxf(cmax2, cn[j]);
+  const float cmax = sqrtf(cmax2) * 1.0000002f;
+  constexpr float kTerms = (float)(NP / 4 + 2);
+  const float gam = kTerms * kU / (1.f - kTerms * kU);
+  const float kB = 2.f * (2.f * gam + 2.f * kU);
+  const bool vec = a.vec != 0;
+
+  for (int64_t base = p_begin; base < p_end; base += kWG) {
+    double fpart = 0.0;
+    int near = 0;
+    const int64_t i = base + threadIdx.x;
+    const bool valid = i < p_end;
+    float x[NP];
+    if (valid && vec) {
+      const float4* src = reinterpret_cast<const float4*>(S + i * (int64_t)NP);
+#pragma unroll
+      for (int q = 0; q < NP / 4; ++q) {
+        const float4 v = src[q];
+        x[4 * q] = v.x;
+        x[4 * q + 1] = v.y;
+        x[4 * q + 2] = v.z;
+        x[4 * q + 3] = v.w;
+      }
+    } else {
+#pragma unroll
+      for (int d = 0; d < NP; ++d) x[d] = (valid && d < n) ? S[i * (int64_t)ld + d] : 0.f;
+    }
+
+    // best and second-best expanded-form values
+    float e1 = __builtin_inff(), e2 = __builtin_inff();
+    int j1 = 0;
+    for (int j = 0; j < k; ++j) {
+      const float e = fmaf(-2.f, dot_reg<NP>(x, C + j * NP), cn[j]);
+      const bool better = e < e1;
+      e2 = better ? e1 : fminf(e2, e);
+      j1 = better ? j : j1;
+      e1 = better ? e : e1;
+    }
+    float xx = 0.f;
+#pragma unroll
+    for (int d = 0; d < NP; ++d) xx = fmaf(x[d], x[d], xx);
+    const float B = kB * (sqrtf(xx) * cmax + cmax2);
+    const bool recheck = valid && !((e2 - e1) > 2.f * B + 2.5e-5f * fabsf(e2 + xx));
+    if (recheck) {
+      float b1 = __builtin_inff(), b2 = __builtin_inff();
+      int jb = 0;
+      for (int j = 0; j < k; ++j) {
+        const float dd = dist_direct_reg<NP>(x, C + j * NP);
+        if (dd < b1) {
+          b2 = b1;
+          b1 = dd;
+          jb = j;
+        } else if (dd < b2) {
+          b2 = dd;
+        }
+      }
+      j1 = jb;
+      if (b2 - b1 < 1e-5f * b2) ++near;
+    }
+    if (valid) {
+      const float d1 = dist_direct_reg<NP>(x, C + j1 * NP);
+      fpart += (double)d1;
+      if (a.labels) a.labels[job * a.lab_stride + i] = j1;
+      if (SUMS) {
+#pragma unroll
+        for (int d = 0; d < NP; ++d) {
+          if (d < n) {
+            const long long q = __double2ll_rn((double)x[d] * a.scale[d]);
+            atomicAdd(&lds_acc[j1 * NP + d], (unsigned long long)q);
+          }
+        }
+        atomicAdd(&lds_cnt[j1], 1u);
+      }
+    }
+    // objective and near-tie count of this 256-point chunk
+    const double ft = block_sum_f64(fpart, red_f);
+    const int nt = block_sum_i32(near, red_i);
+    if (threadIdx.x == 0) {
+      const int64_t ch = (int64_t)job * a.max_chunks + base / kWG;
+      a.tf[ch] = ft;
+      if (a.tnear) a.tnear[ch] = nt;
+    }
+  }
+
+  if (SUMS) {
+    // block_sum_* ended with a barrier, so the LDS sums are complete
+    const int64_t slot = (int64_t)job * a.max_tiles + t;
+    unsigned long long* dst = a.acc + slot * (int64_t)k * NP;
+    for (int e = threadIdx.x; e < k * NP; e += kWG) dst[e] = lds_acc[e];
+    int32_t* cdst = a.cnt + slot * k;
+    for (int e = threadIdx.x; e < k; e += kWG) cdst[e] = (int32_t)lds_cnt[e];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Lloyd finalize.  Grid (nchunks, jobs); chunk c owns centroids
+// [c*kc, (c+1)*kc) with one thread per (centroid, padded dimension).
+// Every workgroup of a job computes the same f (fixed-order tile sum) and the
+// same decision; the last workgroup to arrive commits the job state.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kWG) void k_finalize(FinalizeArgs a) {
+  const int job = blockIdx.y;
+  const int chunk = blockIdx.x;
+  JobState st = a.st[job];
+  if (!st.active) return;
+  const int nt = st.ntiles;
+  const int k = a.k, cp = a.cp;
+  __shared__ double sh_f;
+  __shared__ int sh_upd;
+  __shared__ int sh_cnt[kWG];
+  __shared__ double sh_sq[kWG];
+  __shared__ int sh_last;
+  if (threadIdx.x < 64) {
+    const double f = wave_chunked_sum(a.tf + (int64_t)job * a.max_chunks, st.nchunks);
+    const bool stop = (st.iter > 0 && st.f_prev - f <= a.tol * f) || !isfinite(f) ||
+                      st.iter >= a.max_iter;
+    if (threadIdx.x == 0) {
+      sh_f = f;
+      sh_upd = stop ? 0 : 1;
+    }
+  }
+  __syncthreads();
+  const int upd = sh_upd;
+  const int jj = threadIdx.x / cp;
+  const int d = threadIdx.x - jj * cp;
+  const int j = chunk * a.kc + jj;
+  const bool mine = jj < a.kc && j < k;
+  int cntj = 0;
+  if (mine && d == 0) {
+    for (int t = 0; t < nt; ++t) cntj += a.cnt[((int64_t)job * a.max_tiles + t) * k + j];
+    sh_cnt[jj] = cntj;
+  }
+  __syncthreads();
+  double sq = 0.0;
+  if (mine) {
+    cntj = sh_cnt[jj];
+    float* c = a.Cp + ((int64_t)job * k + j) * cp + d;
+    if (upd) {
+      if (cntj > 0) {
+        unsigned long long sum = 0ull;
+        for (int t = 0; t < nt; ++t)
+          sum += a.acc[(((int64_t)job * a.max_tiles + t) * k + j) * cp + d];
+        const double mean = ((double)(long long)sum * a.inv_scale[d]) / (double)cntj;
+        *c = (float)mean;
+      }
+      const double cv = *c;
+      sq = cv * cv;
+    } else if (d == 0) {
+      a.deg[(int64_t)job * k + j] = cntj == 0 ? 1 : 0;
+    }
+  }
+  sh_sq[threadIdx.x] = sq;
+  __syncthreads();
+  if (upd && mine && d == 0) {
+    double acc = 0.0;
+    for (int q = 0; q < cp; ++q) acc += sh_sq[jj * cp + q];
+    a.cn[(int64_t)job * k + j] = (float)acc;
+  }
+  if (!upd && threadIdx.x == 0) {
+    int empty = 0;
+    for (int q = 0; q < a.kc && chunk * a.kc + q < k; ++q) empty += sh_cnt[q] == 0 ? 1 : 0;
+    if (empty) atomicAdd(&a.ndeg_acc[job], empty);
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int prev = atomicAdd(&a.counter[job], 1);
+    sh_last = (prev == a.nchunks - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (sh_last && threadIdx.x == 0) {
+    __threadfence();
+    a.counter[job] = 0;
+    st.f = sh_f;
+    if (upd) {
+      st.f_prev = sh_f;
+      st.iter += 1;
+    } else {
+      st.active = 0;
+      st.ndeg = atomicAdd(&a.ndeg_acc[job], 0);
+      a.ndeg_acc[job] = 0;
+    }
+    a.st[job] = st;
+  }
+}
+
+__global__ void k_job_init(JobState* js, const int32_t* ntiles, const int64_t* sizes, int njobs,
+                           int32_t* counter, int32_t* ndeg_acc) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= njobs) return;
+  JobState st;
+  st.f = 0.0;
+  st.f_prev = 0.0;
+  st.iter = 0;
+  st.active = 1;
+  st.ndeg = 0;
+  st.ntiles = ntiles[j];
+  st.nchunks = (int32_t)((sizes[j] + kWG - 1) / kWG);
+  st.pad_ = 0;
+  js[j] = st;
+  counter[j] = 0;
+  ndeg_acc[j] = 0;
+}
+
+// Objective of each job: fixed-order sum of its chunk partials (one wave per job).
+__global__ __launch_bounds__(64) void k_reduce_f(const double* __restrict__ tf,
+                                                 const int32_t* __restrict__ tnear,
+                                                 const int64_t* __restrict__ sizes, int max_chunks,
+                                                 double* __restrict__ f,
+                                                 long long* __restrict__ near) {
+  const int j = blockIdx.x;
+  const int64_t nch = (sizes[j] + kWG - 1) / kWG;
+  const double acc = wave_chunked_sum(tf + (int64_t)j * max_chunks, nch);
+  long long nn = 0;
+  if (tnear) {
+    for (int64_t q = threadIdx.x; q < nch; q += 64) nn += tnear[(int64_t)j * max_chunks + q];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) nn += __shfl_xor(nn, off, 64);
+  }
+  if (threadIdx.x == 0) {
+    f[j] = acc;
+    if (near) near[j] = nn;
+  }
+}
+
+// Acceptance (Algorithm 1): replace the incumbent only if f_new < f_hat
+// (strict; a NaN never passes).  status[job] = {accepted, updates, ndeg}.
+__global__ __launch_bounds__(kWG) void k_accept(const float* __restrict__ Cp, int cp, int n, int k,
+                                                const JobState* __restrict__ js,
+                                                const uint8_t* __restrict__ deg_work,
+                                                float* __restrict__ Cinc,
+                                                uint8_t* __restrict__ deg_inc,
+                                                double* __restrict__ fhat,
+                                                int32_t* __restrict__ status) {
+  const int job = blockIdx.x;
+  const JobState st = js[job];
+  const double fh = fhat[job];
+  const bool acc = st.f < fh;
+  __syncthreads();
+  if (acc) {
+    for (int e = threadIdx.x; e < k * n; e += kWG) {
+      const int r = e / n, d = e - r * n;
+      Cinc[(int64_t)job * k * n + e] = Cp[((int64_t)job * k + r) * cp + d];
+    }
+    for (int e = threadIdx.x; e < k; e += kWG) deg_inc[(int64_t)job * k + e] = deg_work[(int64_t)job * k + e];
+  }
+  __syncthreads();
+  __shared__ int red[4];
+  int nd = 0;
+  for (int e = threadIdx.x; e < k; e += kWG) nd += deg_inc[(int64_t)job * k + e] ? 1 : 0;
+  nd = block_sum_i32(nd, red);
+  if (threadIdx.x == 0) {
+    if (acc) fhat[job] = st.f;
+    status[job * 4 + 0] = acc ? 1 : 0;
+    status[job * 4 + 1] = st.iter;
+    status[job * 4 + 2] = nd;
+    status[job * 4 + 3] = 0;
+  }
+}
+
+// Start of a pass: working centroids and degenerate flags from the incumbent.
+__global__ __launch_bounds__(kWG) void k_copy_incumbent(const float* __restrict__ Cinc,
+                                                         const uint8_t* __restrict__ deg_inc,
+                                                         int n, int cp, int k,
+                                                         float* __restrict__ Cp,
+                                                         float* __restrict__ cn,
+                                                         uint8_t* __restrict__ deg_work) {
+  const int job = blockIdx.x;
+  for (int e = threadIdx.x; e < k * cp; e += kWG) {
+    const int r = e / cp, d = e - r * cp;
+    Cp[(int64_t)job * k * cp + e] = d < n ? Cinc[((int64_t)job * k + r) * n + d] : 0.f;
+  }
+  for (int e = threadIdx.x; e < k; e += kWG) deg_work[(int64_t)job * k + e] = deg_inc[(int64_t)job * k + e];
+  for (int r = threadIdx.x; r < k; r += kWG) {
+    double acc = 0.0;
+    for (int d = 0; d < n; ++d) {
+      const double v = Cinc[((int64_t)job * k + r) * n + d];
+      acc += v * v;
+    }
+    cn[(int64_t)job * k + r] = (float)acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Greedy K-means++.  D lives in one of four slots; a step writes the three
+// candidates' updated D into the other three slots together with per-tile
+// FP64 sums, and the next step keeps the slot of the winning candidate.
+// ---------------------------------------------------------------------------
+__device__ inline int other_slot(int dcur, int c) { return c < dcur ? c : c + 1; }
+
+__global__ __launch_bounds__(kWG) void k_kpp_setup(KppArgs a) {
+  const int job = blockIdx.x;
+  const int k = a.k;
+  if (a.picks) {
+    for (int e = threadIdx.x; e < 4 * k; e += kWG) a.picks[(int64_t)job * 4 * k + e] = -1;
+  }
+  if (threadIdx.x == 0) {
+    int nt = 0;
+    for (int j = 0; j < k; ++j)
+      if (a.deg[(int64_t)job * k + j]) a.todo[(int64_t)job * k + nt++] = j;
+    KppState ks;
+    ks.T = 0.0;
+    ks.pot[0] = ks.pot[1] = ks.pot[2] = 0.0;
+    ks.cand[0] = ks.cand[1] = ks.cand[2] = -1;
+    ks.ncand = 0;
+    ks.dcur = 0;
+    ks.ntodo = nt;
+    ks.has_d = nt < k ? 1 : 0;
+    ks.step = 0;
+    ks.pad_ = 0;
+    a.ks[job] = ks;
+  }
+}
+
+// D_i = min over kept centroids of ||S_i - c_j||^2 (slot 0) and tile sums.
+__global__ __launch_bounds__(kWG) void k_kpp_init(KppArgs a) {
+  const int job = blockIdx.y;
+  const KppState ks = a.ks[job];
+  if (ks.ntodo == 0 || !ks.has_d) return;
+  const int64_t s = a.s[job];
+  const int64_t i = (int64_t)blockIdx.x * kDTile + threadIdx.x;
+  if ((int64_t)blockIdx.x * kDTile >= s) return;
+  const float* S = a.S + job * a.S_stride;
+  const float* C = a.Cp + job * a.C_stride;
+  const uint8_t* deg = a.deg + (int64_t)job * a.k;
+  float dmin = __builtin_inff();
+  if (i < s) {
+    for (int j = 0; j < a.k; ++j)
+      if (!deg[j]) dmin = min_nan(dmin, dist_direct_mem(S + i * a.ld, C + (int64_t)j * a.cp, a.n));
+    a.D[0 * a.D_slot_stride + job * a.D_job_stride + i] = dmin;
+  }
+  __shared__ double red[4];
+  const double ts = block_sum_f64(i < s ? (double)dmin : 0.0, red);
+  if (threadIdx.x == 0) a.Dt[(0 * (int64_t)a.njobs + job) * a.ndt_max + blockIdx.x] = ts;
+}
+
+// Wave-level monotone prefix over v[0..cnt): lane l sums a contiguous chunk
+// sequentially; the lane carries are a sequential sum of the chunk totals.
+// Returns the total (uniform).  If tau >= 0 is given, *first receives the
+// first index whose running prefix exceeds tau (or -1) and *before the
+// prefix just before it.
+template <typename T>
+__device__ inline double wave_prefix_search(const T* v, int64_t cnt, double tau, int64_t* first,
+                                            double* before) {
+  const int lane = threadIdx.x & 63;
+  const int64_t cs = (cnt + 63) / 64;
+  const int64_t lo = min(cnt, (int64_t)lane * cs), hi = min(cnt, lo + cs);
+  double tot = 0.0;
+  for (int64_t q = lo; q < hi; ++q) tot += (double)v[q];
+  double carry = 0.0, total = 0.0;
+  for (int l = 0; l < 64; ++l) {
+    const double tl = __shfl(tot, l, 64);
+    if (l == lane) carry = total;
+    total += tl;
+  }
+  if (first) {
+    int64_t found = -1;
+    double bef = 0.0;
+    double r = carry;
+    for (int64_t q = lo; q < hi; ++q) {
+      const double prev = r;
+      r += (double)v[q];
+      if (r > tau) {
+        found = q;
+        bef = prev;
+        break;
+      }
+    }
+    // smallest lane that found a crossing
+    int64_t best = found >= 0 ? found : INT64_MAX;
+    double bbef = bef;
+    for (int off = 32; off > 0; off >>= 1) {
+      const int64_t ob = __shfl_xor(best, off, 64);
+      const double obf = __shfl_xor(bbef, off, 64);
+      if (ob < best) {
+        best = ob;
+        bbef = obf;
+      }
+    }
+    *first = best == INT64_MAX ? -1 : best;
+    *before = bbef;
+  }
+  return total;
+}
+
+// One workgroup per job: commit the pending step, then draw the next one.
+// Only wave 0 works (scans and searches are wave-level).
+__global__ __launch_bounds__(64) void k_kpp_step(KppArgs a) {
+  const int job = blockIdx.x;
+  KppState ks = a.ks[job];
+  const int64_t s = a.s[job];
+  const int k = a.k;
+  const int64_t ndt = (s + kDTile - 1) / kDTile;
+  const float* S = a.S + job * a.S_stride;
+  const int lane = threadIdx.x;
+  if (ks.ncand > 0) {
+    for (int c = 0; c < ks.ncand; ++c) {
+      const int sl = other_slot(ks.dcur, c);
+      ks.pot[c] = wave_prefix_search<double>(a.Dt + ((int64_t)sl * a.njobs + job) * a.ndt_max,
+                                             ndt, -1.0, nullptr, nullptr);
+    }
+    int best = 0;
+    for (int c = 1; c < ks.ncand; ++c)
+      if (ks.pot[c] < ks.pot[best]) best = c;
+    const int j = a.todo[(int64_t)job * k + ks.step - 1];
+    const int64_t istar = ks.cand[best];
+    float* cj = a.Cp + job * a.C_stride + (int64_t)j * a.cp;
+    for (int d = lane; d < a.cp; d += 64) cj[d] = d < a.n ? S[istar * a.ld + d] : 0.f;
+    if (lane == 0) {
+      a.deg[(int64_t)job * k + j] = 0;
+      if (a.picks) {
+        int32_t* p = a.picks + ((int64_t)job * k + j) * 4;
+        p[0] = (int32_t)istar;
+        for (int c = 0; c < 3; ++c) p[1 + c] = (ks.ncand > 1 && c < ks.ncand) ? ks.cand[c] : -1;
+      }
+    }
+    ks.dcur = other_slot(ks.dcur, best);
+    ks.T = ks.pot[best];
+    ks.has_d = 1;
+    ks.ncand = 0;
+  }
+  if (ks.step < ks.ntodo) {
+    uint64_t k0, k1;
+    stream_key(a.seed_worker[job * 2], (uint32_t)a.seed_worker[job * 2 + 1], 3u, &k0, &k1);
+    const U64x4 w = philox_ctr((uint64_t)ks.step, a.g, 0, 0, k0, k1);
+    const double* dt = a.Dt + ((int64_t)ks.dcur * a.njobs + job) * a.ndt_max;
+    if (ks.has_d && ks.step == 0) ks.T = wave_prefix_search<double>(dt, ndt, -1.0, nullptr, nullptr);
+    if (!ks.has_d || !(ks.T > 0.0 && ks.T < __builtin_inf())) {
+      ks.ncand = 1;
+      ks.cand[0] = (int32_t)bounded(w.w[3], (uint64_t)s);
+      ks.cand[1] = ks.cand[2] = -1;
+    } else {
+      ks.ncand = a.n_cand;
+      const float* Dj = a.D + (int64_t)ks.dcur * a.D_slot_stride + job * a.D_job_stride;
+      for (int c = 0; c < a.n_cand; ++c) {
+        const double tau = u01(w.w[c]) * ks.T;
+        int64_t tile;
+        double base;
+        wave_prefix_search<double>(dt, ndt, tau, &tile, &base);
+        if (tile < 0) {  // rounding put tau at the very end: last tile with mass,
+          tile = ndt - 1;  // whose first point with D > 0 is taken below
+          while (tile > 0 && !(dt[tile] > 0.0)) --tile;
+          base = tau;
+        }
+        const int64_t lo = tile * kDTile;
+        const int64_t cnt = min((int64_t)kDTile, s - lo);
+        int64_t within;
+        double bef;
+        // running prefix inside the tile, started at the tile's base
+        const double tin = tau - base;
+        wave_prefix_search<float>(Dj + lo, cnt, tin, &within, &bef);
+        if (within < 0) {  // fallback: last point of the tile with D > 0
+          within = cnt - 1;
+          while (within > 0 && !(Dj[lo + within] > 0.f)) --within;
+        }
+        ks.cand[c] = (int32_t)(lo + within);
+      }
+      for (int c = a.n_cand; c < 3; ++c) ks.cand[c] = -1;
+    }
+    ks.step += 1;
+  }
+  if (lane == 0) a.ks[job] = ks;
+}
+
+// Potentials of the pending candidates: new D per candidate into the other
+// slots, with per-tile sums.
+__global__ __launch_bounds__(kWG) void k_kpp_pot(KppArgs a) {
+  const int job = blockIdx.y;
+  const KppState ks = a.ks[job];
+  if (ks.ncand == 0) return;
+  const int64_t s = a.s[job];
+  if ((int64_t)blockIdx.x * kDTile >= s) return;
+  const int64_t i = (int64_t)blockIdx.x * kDTile + threadIdx.x;
+  const float* S = a.S + job * a.S_stride;
+  __shared__ double red[4];
+  float dcur = 0.f;
+  if (i < s && ks.has_d) dcur = a.D[(int64_t)ks.dcur * a.D_slot_stride + job * a.D_job_stride + i];
+  for (int c = 0; c < ks.ncand; ++c) {
+    const float* xc = S + (int64_t)ks.cand[c] * a.ld;
+    float m = 0.f;
+    if (i < s) {
+      const float dc = dist_direct_mem(S + i * a.ld, xc, a.n);
+      m = ks.has_d ? min_nan(dcur, dc) : dc;
+      a.D[(int64_t)other_slot(ks.dcur, c) * a.D_slot_stride + job * a.D_job_stride + i] = m;
+    }
+    const double ts = block_sum_f64(i < s ? (double)m : 0.0, red);
+    if (threadIdx.x == 0)
+      a.Dt[((int64_t)other_slot(ks.dcur, c) * a.njobs + job) * a.ndt_max + blockIdx.x] = ts;
+  }
+}
+
+template <int NP>
+hipError_t launch_assign_np(hipStream_t st, const AssignArgs& a, int ntiles, bool sums) {
+  if (sums) {
+    const size_t lds = (size_t)a.k * NP * 8 + (size_t)a.k * 4;
+    if (lds > 64 * 1024) {
+      hipError_t e = hipFuncSetAttribute((const void*)k_assign_small<NP, true>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_assign_small<NP, true>), dim3(ntiles), dim3(kWG), lds, st, a);
+  } else {
+    hipLaunchKernelGGL((k_assign_small<NP, false>), dim3(ntiles), dim3(kWG), 0, st, a);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_sample(hipStream_t st, const float* X, int64_t m, int32_t n, int32_t njobs,
+                         int64_t max_s, const int64_t* s, const uint64_t* rkeys, int32_t* idx,
+                         int64_t idx_stride, float* S, int64_t S_stride, int32_t ld) {
+  const dim3 grid((unsigned)((max_s + kWG - 1) / kWG), (unsigned)njobs);
+  const bool vec = (n % 4 == 0) && (ld % 4 == 0) && (((uintptr_t)X & 15) == 0) &&
+                   (S == nullptr || ((uintptr_t)S & 15) == 0) && (S_stride % 4 == 0);
+  if (vec)
+    hipLaunchKernelGGL(k_sample<true>, grid, dim3(kWG), 0, st, X, m, n, s, rkeys, idx, idx_stride,
+                       S, S_stride, ld);
+  else
+    hipLaunchKernelGGL(k_sample<false>, grid, dim3(kWG), 0, st, X, m, n, s, rkeys, idx,
+                       idx_stride, S, S_stride, ld);
+  return hipGetLastError();
+}
+
+hipError_t launch_absmax(hipStream_t st, const float* X, int64_t rows, int32_t n, int32_t ld,
+                         unsigned int* absmax_bits) {
+  const int64_t total = rows * n;
+  int64_t blocks = (total + kWG - 1) / kWG;
+  if (blocks > 2048) blocks = 2048;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_absmax, dim3((unsigned)blocks), dim3(kWG), (size_t)n * 4, st, X, rows, n,
+                     ld, absmax_bits);
+  return hipGetLastError();
+}
+
+hipError_t launch_scales(hipStream_t st, const unsigned int* absmax_bits, int32_t n, int32_t cp,
+                         int64_t max_s, double* scale, double* inv_scale) {
+  hipLaunchKernelGGL(k_scales, dim3((cp + 255) / 256), dim3(256), 0, st, absmax_bits, n, cp,
+                     max_s, scale, inv_scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_pad_centroids(hipStream_t st, const float* C, int64_t C_stride, int32_t n,
+                                int32_t cp, int32_t k, int32_t njobs, float* Cp, int64_t Cp_stride,
+                                float* cn, int64_t cn_stride) {
+  hipLaunchKernelGGL(k_pad_centroids, dim3(njobs), dim3(kWG), 0, st, C, C_stride, n, cp, k, Cp,
+                     Cp_stride, cn, cn_stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_centroid_norms(hipStream_t st, const float* Cp, int32_t cp, int32_t k,
+                                 int32_t njobs, float* cn) {
+  hipLaunchKernelGGL(k_centroid_norms, dim3(njobs), dim3(kWG), 0, st, Cp, cp, k, cn);
+  return hipGetLastError();
+}
+
+hipError_t launch_assign(hipStream_t st, const AssignArgs& a, int32_t ntiles, bool sums) {
+  switch (a.cp) {
+#define BM_CASE(NPV) \
+  case NPV:          \
+    return launch_assign_np<NPV>(st, a, ntiles, sums);
+    BM_CASE(4)
+    BM_CASE(8)
+    BM_CASE(12)
+    BM_CASE(16)
+    BM_CASE(20)
+    BM_CASE(24)
+    BM_CASE(28)
+    BM_CASE(32)
+    BM_CASE(36)
+    BM_CASE(40)
+    BM_CASE(44)
+    BM_CASE(48)
+    BM_CASE(52)
+    BM_CASE(56)
+    BM_CASE(60)
+    BM_CASE(64)
+#undef BM_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_finalize(hipStream_t st, const FinalizeArgs& a, int32_t njobs) {
+  hipLaunchKernelGGL(k_finalize, dim3(a.nchunks, njobs), dim3(kWG), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_job_init(hipStream_t st, JobState* js, const int32_t* ntiles,
+                           const int64_t* sizes, int32_t njobs, int32_t* counter,
+                           int32_t* ndeg_acc) {
+  hipLaunchKernelGGL(k_job_init, dim3((njobs + 63) / 64), dim3(64), 0, st, js, ntiles, sizes,
+                     njobs, counter, ndeg_acc);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_f(hipStream_t st, const double* tf, const int32_t* tnear,
+                           const int64_t* sizes, int32_t max_chunks, int32_t njobs, double* f,
+                           long long* near) {
+  hipLaunchKernelGGL(k_reduce_f, dim3(njobs), dim3(64), 0, st, tf, tnear, sizes, max_chunks, f,
+                     near);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpad(hipStream_t st, const float* Cp, int32_t cp, int32_t n, int32_t k,
+                        int32_t njobs, float* C, int64_t C_stride) {
+  hipLaunchKernelGGL(k_unpad, dim3(njobs), dim3(kWG), 0, st, Cp, cp, n, k, C, C_stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_accept(hipStream_t st, const float* Cp, int32_t cp, int32_t n, int32_t k,
+                         int32_t njobs, const JobState* js, const uint8_t* deg_work, float* Cinc,
+                         uint8_t* deg_inc, double* fhat, int32_t* status) {
+  hipLaunchKernelGGL(k_accept, dim3(njobs), dim3(kWG), 0, st, Cp, cp, n, k, js, deg_work, Cinc,
+                     deg_inc, fhat, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_incumbent(hipStream_t st, const float* Cinc, const uint8_t* deg_inc,
+                                 int32_t n, int32_t cp, int32_t k, int32_t njobs, float* Cp,
+                                 float* cn, uint8_t* deg_work) {
+  hipLaunchKernelGGL(k_copy_incumbent, dim3(njobs), dim3(kWG), 0, st, Cinc, deg_inc, n, cp, k, Cp,
+                     cn, deg_work);
+  return hipGetLastError();
+}
+
+hipError_t launch_kpp_setup(hipStream_t st, const KppArgs& a, int32_t njobs) {
+  hipLaunchKernelGGL(k_kpp_setup, dim3(njobs), dim3(kWG), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_kpp_init(hipStream_t st, const KppArgs& a, int32_t njobs, int64_t max_s) {
+  const dim3 grid((unsigned)((max_s + kDTile - 1) / kDTile), (unsigned)njobs);
+  hipLaunchKernelGGL(k_kpp_init, grid, dim3(kWG), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_kpp_step(hipStream_t st, const KppArgs& a, int32_t njobs) {
+  hipLaunchKernelGGL(k_kpp_step, dim3(njobs), dim3(64), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_kpp_pot(hipStream_t st, const KppArgs& a, int32_t njobs, int64_t max_s) {
+  const dim3 grid((unsigned)((max_s + kDTile - 1) / kDTile), (unsigned)njobs);
+  hipLaunchKernelGGL(k_kpp_pot, grid, dim3(kWG), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace bm
