@@ -222,6 +222,26 @@ BM_API int bm_bigmeans_run(bm_ctx* ctx, const float* X, const bm_params* params,
                            float* C_best_out, int32_t* Y_out, bm_result* out,
                            bm_trace_cb cb, void* user);
 
+/* Kernel timing of the Lloyd assignment (the dominant kernel), for
+ * measurement.  With profiling on, every assignment launch of a Lloyd
+ * iteration is bracketed by HIP events on the context's stream and the
+ * device time is accumulated; enabling resets the counters.  Counters:
+ *   assign_launches  assignment kernel launches
+ *   assign_seconds   their summed device time
+ *   assign_dists     point-centre distances those launches computed for
+ *                    active jobs (sum over jobs of s * k per assignment)
+ *   finalize_seconds summed device time of the update/convergence kernel
+ * Profiling adds event records between launches; leave it off otherwise. */
+typedef struct bm_stats {
+  int64_t assign_launches;
+  int64_t assign_dists;
+  double assign_seconds;
+  double finalize_seconds;
+} bm_stats;
+
+BM_API int bm_set_profiling(bm_ctx* ctx, int on);
+BM_API int bm_get_stats(bm_ctx* ctx, bm_stats* out);
+
 /* Host-only: the sample size of `worker` in round t under params' policy,
  * given the BINS statistics so far (bin_acc/bin_passes: 5 counts each, may
  * be NULL for other policies).  Writes the size and its bin (0..4).  Needs no

@@ -36,6 +36,11 @@ class Result(ct.Structure):
                 ("gpu_seconds", ct.c_double), ("lloyd_seconds", ct.c_double)]
 
 
+class Stats(ct.Structure):
+    _fields_ = [("assign_launches", ct.c_int64), ("assign_dists", ct.c_int64),
+                ("assign_seconds", ct.c_double), ("finalize_seconds", ct.c_double)]
+
+
 TRACE_CB = ct.CFUNCTYPE(None, ct.c_void_p, ct.c_int32, ct.c_void_p,
                         ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64), ct.c_double)
 
@@ -64,6 +69,8 @@ SIGNATURES = [
     ("bm_draw_size", ct.c_int, [ct.POINTER(Params), ct.c_uint32, ct.c_int32,
                                 ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int64),
                                 ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int32)]),
+    ("bm_set_profiling", ct.c_int, [ct.c_void_p, ct.c_int]),
+    ("bm_get_stats", ct.c_int, [ct.c_void_p, ct.POINTER(Stats)]),
     ("bm_philox4x64", None, [ct.POINTER(ct.c_uint64), ct.POINTER(ct.c_uint64),
                              ct.POINTER(ct.c_uint64)]),
 ]

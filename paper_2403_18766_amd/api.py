@@ -211,6 +211,22 @@ def _copy_device(dst, src_ptr, nbytes):
         raise RuntimeError(f"hipMemcpy failed ({rc})")
 
 
+def set_profiling(device, on=True):
+    """bm_set_profiling on the context of (device, current stream); resets counters."""
+    device = torch.device(device)
+    lib, c = _ctx(device)
+    _check(lib, c, lib.bm_set_profiling(c, 1 if on else 0))
+
+
+def get_stats(device):
+    """bm_get_stats: dict of the Lloyd kernel timing counters."""
+    device = torch.device(device)
+    lib, c = _ctx(device)
+    st = _lib.Stats()
+    _check(lib, c, lib.bm_get_stats(c, ct.byref(st)))
+    return {f: getattr(st, f) for f, _ in _lib.Stats._fields_}
+
+
 def draw_size(params, m, n, worker, t, bin_acc=None, bin_passes=None):
     """bm_draw_size (host only): the sample size of `worker` in round t and its bin."""
     lib = _lib.load()

@@ -54,9 +54,8 @@ struct bm_ctx {
   int64_t obj_chunks = 0;  // chunks reserved for a full-data objective
 
   // device workspace
-  DevBuf S, idx, labels, Cp, cn, Cinc, deg_work, deg_inc, fhat, acc, cnt, tf, tnear, js, counter,
-      ndeg_acc, ntiles, sizes, tile_job, tile_idx, rkeys, seed_worker, absmax, scale, inv_scale,
-      fjob, nearjob, status, D, Dt, ks, todo, picks;
+  DevBuf S, idx, labels, Cp, cn, Cinc, deg_work, deg_inc, fhat, acc, cnt, tf, tnear, js, sizes, tile_job, tile_idx, rkeys, seed_worker, absmax, scale, inv_scale,
+      fjob, nearjob, D, Dt, ks, todo, picks;
   int64_t tile_cap = 0;  // entries of tile_job / tile_idx
 
   // pinned staging ring
@@ -69,6 +68,11 @@ struct bm_ctx {
   size_t rb_bytes = 0;
 
   hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
+
+  // profiling of the Lloyd kernels (bm_set_profiling)
+  bool prof = false;
+  std::vector<hipEvent_t> pev;  // 3 events per iteration: before assign, after assign, after finalize
+  bm_stats stats{};
 
   int fail(int code, const char* fmt, ...) {
     char buf[512];
@@ -168,7 +172,7 @@ int reserve_impl(bm_ctx* c, int64_t max_s, int max_n, int max_k, int max_jobs) {
   const int cp = round_up4(max_n);
   const int64_t mc = (max_s + bm::kWG - 1) / bm::kWG;
   const size_t J = (size_t)max_jobs;
-  const size_t T = (size_t)bm::kMaxTiles;
+  const size_t T = 256;  // initial tile-map capacity per job
   BM_TRY(dev_alloc(c, c->S, J * max_s * cp * sizeof(float)));
   BM_TRY(dev_alloc(c, c->idx, J * max_s * sizeof(int32_t)));
   BM_TRY(dev_alloc(c, c->labels, J * max_s * sizeof(int32_t)));
@@ -178,15 +182,12 @@ int reserve_impl(bm_ctx* c, int64_t max_s, int max_n, int max_k, int max_jobs) {
   BM_TRY(dev_alloc(c, c->deg_work, J * max_k));
   BM_TRY(dev_alloc(c, c->deg_inc, J * max_k));
   BM_TRY(dev_alloc(c, c->fhat, J * sizeof(double)));
-  BM_TRY(dev_alloc(c, c->acc, J * T * max_k * cp * sizeof(unsigned long long)));
-  BM_TRY(dev_alloc(c, c->cnt, J * T * max_k * sizeof(int32_t)));
+  BM_TRY(dev_alloc(c, c->acc, J * max_k * cp * sizeof(unsigned long long)));
+  BM_TRY(dev_alloc(c, c->cnt, J * max_k * sizeof(int32_t)));
   const size_t tfn = std::max<size_t>(J * mc, (size_t)c->obj_chunks);
   BM_TRY(dev_alloc(c, c->tf, tfn * sizeof(double)));
   BM_TRY(dev_alloc(c, c->tnear, tfn * sizeof(int32_t)));
   BM_TRY(dev_alloc(c, c->js, J * sizeof(JobState)));
-  BM_TRY(dev_alloc(c, c->counter, J * sizeof(int32_t)));
-  BM_TRY(dev_alloc(c, c->ndeg_acc, J * sizeof(int32_t)));
-  BM_TRY(dev_alloc(c, c->ntiles, J * sizeof(int32_t)));
   BM_TRY(dev_alloc(c, c->sizes, J * sizeof(int64_t)));
   const int64_t tcap = std::max<int64_t>((int64_t)J * T, c->tile_cap);
   BM_TRY(dev_alloc(c, c->tile_job, tcap * sizeof(int32_t)));
@@ -199,7 +200,6 @@ int reserve_impl(bm_ctx* c, int64_t max_s, int max_n, int max_k, int max_jobs) {
   BM_TRY(dev_alloc(c, c->inv_scale, (size_t)cp * sizeof(double)));
   BM_TRY(dev_alloc(c, c->fjob, J * sizeof(double)));
   BM_TRY(dev_alloc(c, c->nearjob, J * sizeof(long long)));
-  BM_TRY(dev_alloc(c, c->status, J * 4 * sizeof(int32_t)));
   BM_TRY(dev_alloc(c, c->D, 4 * J * max_s * sizeof(float)));
   BM_TRY(dev_alloc(c, c->Dt, 4 * J * mc * sizeof(double)));
   BM_TRY(dev_alloc(c, c->ks, J * sizeof(KppState)));
@@ -231,23 +231,18 @@ int ensure_objective(bm_ctx* c, int64_t m) {
   return BM_OK;
 }
 
-// Points per assignment workgroup: enough workgroups to fill the chip
-// (about 8 per compute unit over the whole batch).  Lloyd batches keep at
-// most kMaxTiles workgroups per job (the bound of the partial-sum buffers).
-int choose_tile_pts(const std::vector<int64_t>& sizes, bool bounded) {
-  int64_t total = 0, smax = 1;
-  for (int64_t s : sizes) {
-    total += s;
-    smax = std::max(smax, s);
-  }
-  const int64_t target = 2048;
-  int64_t chunks = (total + bm::kWG * target - 1) / (bm::kWG * target);
-  chunks = std::max<int64_t>(chunks, 1);
-  if (bounded) {
-    const int64_t per = (int64_t)bm::kWG * bm::kMaxTiles;
-    chunks = std::max(chunks, (smax + per - 1) / per);
-  }
-  return (int)(chunks * bm::kWG);
+// Points per assignment workgroup: a multiple of 512 (two 256-point chunks,
+// one per register-blocked point of a lane), large enough that the whole
+// batch fits in about 1,024 workgroups, i.e. one residency round of the
+// chip (256 compute units x 4 workgroups at the kernel's register use).
+int choose_tile_pts(const std::vector<int64_t>& sizes) {
+  int64_t total = 0;
+  for (int64_t s : sizes) total += s;
+  const int64_t step = 2 * bm::kWG;
+  const int64_t target = 1024;
+  int64_t steps = (total + step * target - 1) / (step * target);
+  steps = std::max<int64_t>(steps, 1);
+  return (int)(steps * step);
 }
 
 struct TileMap {
@@ -313,20 +308,25 @@ struct BatchView {
 
 // Run Lloyd on every job of the batch from the centroids in Cp (slots
 // first..first+njobs-1).  Leaves the final centroids in Cp, the job states in
-// js, degenerate flags in deg_work and optionally labels.
+// js, degenerate flags in deg_work and the final labels in `labels` (or in
+// the workspace label buffer when labels is null).
 int lloyd_batch(bm_ctx* c, const BatchView& b, int max_iter, double tol, int32_t* labels,
-                int64_t lab_stride) {
+                int64_t lab_stride, bool accept = false, std::vector<JobState>* out = nullptr) {
   const int J = b.njobs, first = b.first, k = b.k, cp = b.cp;
-  TileMap tm = make_tiles(b.sizes, choose_tile_pts(b.sizes, true));
+  if (!labels) {
+    labels = P<int32_t>(c->labels) + (int64_t)first * c->max_s;
+    lab_stride = c->max_s;
+  }
+  const int tile_pts = choose_tile_pts(b.sizes);
+  TileMap tm = make_tiles(b.sizes, tile_pts);
   BM_TRY(upload_tiles(c, tm));
-  BM_TRY(upload(c, P<int32_t>(c->ntiles) + first, tm.ntiles.data(), J * sizeof(int32_t)));
   BM_TRY(upload(c, P<int64_t>(c->sizes) + first, b.sizes.data(), J * sizeof(int64_t)));
   JobState* js = P<JobState>(c->js) + first;
-  HIP_TRY(c, bm::launch_job_init(c->stream, js, P<int32_t>(c->ntiles) + first,
-                                 P<int64_t>(c->sizes) + first, J, P<int32_t>(c->counter) + first,
-                                 P<int32_t>(c->ndeg_acc) + first));
-  HIP_TRY(c, bm::launch_centroid_norms(c->stream, P<float>(c->Cp) + (int64_t)first * k * cp, cp, k,
-                                       J, P<float>(c->cn) + (int64_t)first * k));
+  unsigned long long* acc = P<unsigned long long>(c->acc) + (int64_t)first * k * cp;
+  int32_t* cnt = P<int32_t>(c->cnt) + (int64_t)first * k;
+  HIP_TRY(c, bm::launch_job_init(c->stream, js, P<int64_t>(c->sizes) + first, J, k, cp, acc, cnt,
+                                 P<float>(c->Cp) + (int64_t)first * k * cp,
+                                 P<float>(c->cn) + (int64_t)first * k));
   bm::AssignArgs a{};
   a.S = b.S;
   a.S_stride = b.S_stride;
@@ -334,8 +334,7 @@ int lloyd_batch(bm_ctx* c, const BatchView& b, int max_iter, double tol, int32_t
   a.n = b.n;
   a.cp = cp;
   a.k = k;
-  a.tile_pts = tm.tile_pts;
-  a.max_tiles = bm::kMaxTiles;
+  a.tile_pts = tile_pts;
   a.max_chunks = (int32_t)c->max_chunks;
   a.vec = (b.ld == cp && aligned16(b.S) && (b.S_stride % 4) == 0) ? 1 : 0;
   a.s = P<int64_t>(c->sizes) + first;
@@ -349,8 +348,8 @@ int lloyd_batch(bm_ctx* c, const BatchView& b, int max_iter, double tol, int32_t
   a.lab_stride = lab_stride;
   a.tf = P<double>(c->tf) + (int64_t)first * c->max_chunks;
   a.tnear = nullptr;
-  a.acc = P<unsigned long long>(c->acc) + (int64_t)first * bm::kMaxTiles * k * cp;
-  a.cnt = P<int32_t>(c->cnt) + (int64_t)first * bm::kMaxTiles * k;
+  a.acc = acc;
+  a.cnt = cnt;
   a.scale = P<double>(c->scale);
   a.st = js;
 
@@ -358,40 +357,82 @@ int lloyd_batch(bm_ctx* c, const BatchView& b, int max_iter, double tol, int32_t
   f.n = b.n;
   f.cp = cp;
   f.k = k;
-  f.max_tiles = bm::kMaxTiles;
   f.max_chunks = (int32_t)c->max_chunks;
   f.max_iter = max_iter;
-  f.kc = std::max(1, bm::kWG / cp);
-  f.nchunks = (k + f.kc - 1) / f.kc;
   f.tol = tol;
-  f.acc = a.acc;
-  f.cnt = a.cnt;
+  f.acc = acc;
+  f.cnt = cnt;
   f.tf = a.tf;
   f.inv_scale = P<double>(c->inv_scale);
   f.Cp = P<float>(c->Cp) + (int64_t)first * k * cp;
   f.cn = P<float>(c->cn) + (int64_t)first * k;
   f.st = js;
   f.deg = P<uint8_t>(c->deg_work) + (int64_t)first * k;
-  f.counter = P<int32_t>(c->counter) + first;
-  f.ndeg_acc = P<int32_t>(c->ndeg_acc) + first;
+  if (accept) {
+    f.Cinc = P<float>(c->Cinc) + (int64_t)first * k * b.n;
+    f.deg_inc = P<uint8_t>(c->deg_inc) + (int64_t)first * k;
+    f.fhat = P<double>(c->fhat) + first;
+  }
 
   // Each job makes at most max_iter + 1 assignments.  Launch a few
-  // iterations between checks of the job states.
+  // iterations between checks of the job states; after each check the tile
+  // map keeps only the jobs that still iterate.
   std::vector<JobState> hs(J);
+  std::vector<int32_t> prev_iter(J, -1);  // updates seen at the previous check
+  std::vector<int64_t> live(b.sizes);
   int launched = 0;
-  int chunk = 3;
+  int chunk = 4;
   while (true) {
     const int todo = std::min(chunk, max_iter + 1 - launched);
+    if (c->prof && (int)c->pev.size() < 2 * todo) {
+      for (int q = (int)c->pev.size(); q < 2 * todo; ++q) {
+        hipEvent_t e;
+        HIP_TRY(c, hipEventCreate(&e));
+        c->pev.push_back(e);
+      }
+    }
     for (int q = 0; q < todo; ++q) {
+      if (c->prof) HIP_TRY(c, hipEventRecord(c->pev[2 * q], c->stream));
       HIP_TRY(c, bm::launch_assign(c->stream, a, tm.total, true));
+      if (c->prof) HIP_TRY(c, hipEventRecord(c->pev[2 * q + 1], c->stream));
       HIP_TRY(c, bm::launch_finalize(c->stream, f, J));
     }
     launched += todo;
     BM_TRY(readback(c, js, J * sizeof(JobState), hs.data()));
-    bool any = false;
-    for (int j = 0; j < J; ++j) any = any || hs[j].active;
-    if (!any) break;
+    if (c->prof) {
+      for (int q = 0; q < todo; ++q) {
+        float ms_a = 0.f;
+        HIP_TRY(c, hipEventElapsedTime(&ms_a, c->pev[2 * q], c->pev[2 * q + 1]));
+        c->stats.assign_seconds += ms_a * 1e-3;
+        c->stats.assign_launches += 1;
+      }
+      // distances of this chunk: job j made (assignments now - before)
+      for (int j = 0; j < J; ++j) {
+        const int before = prev_iter[j] < 0 ? 0 : prev_iter[j] + 1;
+        const int now = hs[j].iter + 1;
+        if (now > before) c->stats.assign_dists += (int64_t)(now - before) * b.sizes[j] * k;
+        prev_iter[j] = hs[j].iter;
+      }
+    }
+    bool any = false, shrink = false;
+    for (int j = 0; j < J; ++j) {
+      any = any || hs[j].active;
+      if (!hs[j].active && live[j] != 0) {
+        live[j] = 0;
+        shrink = true;
+      }
+    }
+    if (!any) {
+      if (out) *out = hs;
+      break;
+    }
     if (launched >= max_iter + 1) return c->fail(BM_E_STATE, "Lloyd did not stop after %d steps", launched);
+    if (shrink) {
+      // fewer points left: smaller tiles spread them over more compute units
+      a.tile_pts = choose_tile_pts(live);
+      tm = make_tiles(live, a.tile_pts);
+      BM_TRY(upload_tiles(c, tm));
+    }
     chunk = std::min(chunk * 2, 16);
   }
   return BM_OK;
@@ -401,7 +442,7 @@ int lloyd_batch(bm_ctx* c, const BatchView& b, int max_iter, double tol, int32_t
 int objective_batch(bm_ctx* c, const BatchView& b, int32_t* labels, int64_t lab_stride,
                     int64_t max_chunks, bool near) {
   const int J = b.njobs, first = b.first, k = b.k, cp = b.cp;
-  TileMap tm = make_tiles(b.sizes, choose_tile_pts(b.sizes, false));
+  TileMap tm = make_tiles(b.sizes, choose_tile_pts(b.sizes));
   BM_TRY(upload_tiles(c, tm));
   BM_TRY(upload(c, P<int64_t>(c->sizes) + first, b.sizes.data(), J * sizeof(int64_t)));
   bm::AssignArgs a{};
@@ -412,7 +453,6 @@ int objective_batch(bm_ctx* c, const BatchView& b, int32_t* labels, int64_t lab_
   a.cp = cp;
   a.k = k;
   a.tile_pts = tm.tile_pts;
-  a.max_tiles = bm::kMaxTiles;
   a.max_chunks = (int32_t)max_chunks;
   a.vec = (b.ld == cp && aligned16(b.S) && (b.S_stride % 4) == 0) ? 1 : 0;
   a.s = P<int64_t>(c->sizes) + first;
@@ -616,10 +656,10 @@ BM_API void bm_destroy(bm_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   DevBuf* bufs[] = {&c->S,        &c->idx,     &c->labels,   &c->Cp,        &c->cn,
                     &c->Cinc,     &c->deg_work, &c->deg_inc, &c->fhat,      &c->acc,
-                    &c->cnt,      &c->tf,      &c->tnear,    &c->js,        &c->counter,
-                    &c->ndeg_acc, &c->ntiles,  &c->sizes,    &c->tile_job,  &c->tile_idx,
+                    &c->cnt,      &c->tf,      &c->tnear,    &c->js,
+                    &c->sizes,    &c->tile_job,  &c->tile_idx,
                     &c->rkeys,    &c->seed_worker, &c->absmax, &c->scale,   &c->inv_scale,
-                    &c->fjob,     &c->nearjob, &c->status,   &c->D,         &c->Dt,
+                    &c->fjob,     &c->nearjob, &c->D,         &c->Dt,
                     &c->ks,       &c->todo,    &c->picks};
   for (DevBuf* b : bufs) dev_free(*b);
   for (int i = 0; i < kNumStage; ++i) {
@@ -630,6 +670,7 @@ BM_API void bm_destroy(bm_ctx* c) {
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   if (c->ev2) (void)hipEventDestroy(c->ev2);
+  for (hipEvent_t e : c->pev) (void)hipEventDestroy(e);
   delete c;
 }
 
@@ -782,6 +823,19 @@ BM_API void bm_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t
   for (int i = 0; i < 4; ++i) out[i] = y.w[i];
 }
 
+BM_API int bm_set_profiling(bm_ctx* c, int on) {
+  if (!c) return BM_E_ARG;
+  c->prof = on != 0;
+  c->stats = bm_stats{};
+  return BM_OK;
+}
+
+BM_API int bm_get_stats(bm_ctx* c, bm_stats* out) {
+  if (!c || !out) return BM_E_ARG;
+  *out = c->stats;
+  return BM_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Algorithm 1
 // ---------------------------------------------------------------------------
@@ -819,7 +873,6 @@ BM_API int bm_bigmeans_run(bm_ctx* c, const float* X, const bm_params* params, f
     sw[2 * w + 1] = (uint64_t)w;
   }
   std::vector<uint64_t> rk(4 * (size_t)W);
-  std::vector<int32_t> status(4 * (size_t)W);
   const int64_t Sj = c->max_s * cp;  // floats between job samples
   float* Sbase = P<float>(c->S);
 
@@ -895,7 +948,6 @@ BM_API int bm_bigmeans_run(bm_ctx* c, const float* X, const bm_params* params, f
         HIP_TRY(c, bm::launch_copy_incumbent(st, P<float>(c->Cinc) + (int64_t)first * k * n,
                                              P<uint8_t>(c->deg_inc) + (int64_t)first * k, n, cp, k,
                                              J, P<float>(c->Cp) + (int64_t)first * k * cp,
-                                             P<float>(c->cn) + (int64_t)first * k,
                                              P<uint8_t>(c->deg_work) + (int64_t)first * k));
         BatchView b;
         b.first = first;
@@ -910,31 +962,24 @@ BM_API int bm_bigmeans_run(bm_ctx* c, const float* X, const bm_params* params, f
         // K-means++ for degenerate centroids
         KppBatch kb{sw.data() + 2 * first, g, p.n_candidates, steps, nullptr};
         BM_TRY(kpp_batch(c, b, kb));
-        // Lloyd
+        // Lloyd with acceptance (the finalize of each job's last iteration
+        // replaces the incumbent on a strict improvement)
         HIP_TRY(c, hipEventRecord(c->ev1, st));
-        BM_TRY(lloyd_batch(c, b, p.max_iter, p.tol, nullptr, 0));
+        std::vector<JobState> fin;
+        BM_TRY(lloyd_batch(c, b, p.max_iter, p.tol, nullptr, 0, true, &fin));
         HIP_TRY(c, hipEventRecord(c->ev2, st));
-        // accept
-        HIP_TRY(c, bm::launch_accept(st, P<float>(c->Cp) + (int64_t)first * k * cp, cp, n, k, J,
-                                     P<JobState>(c->js) + first,
-                                     P<uint8_t>(c->deg_work) + (int64_t)first * k,
-                                     P<float>(c->Cinc) + (int64_t)first * k * n,
-                                     P<uint8_t>(c->deg_inc) + (int64_t)first * k,
-                                     P<double>(c->fhat) + first, P<int32_t>(c->status) + 4 * first));
-        BM_TRY(readback(c, P<int32_t>(c->status) + 4 * first, 4 * J * sizeof(int32_t),
-                        status.data() + 4 * first));
-        BM_TRY(readback(c, P<double>(c->fhat) + first, J * sizeof(double), fhat.data() + first));
+        HIP_TRY(c, hipEventSynchronize(c->ev2));
         float ms = 0.f;
         HIP_TRY(c, hipEventElapsedTime(&ms, c->ev1, c->ev2));
         lloyd_ms += ms;
         for (int j = 0; j < J; ++j) {
           const int w = first + j;
-          const int32_t* sw4 = &status[4 * w];
-          lloyd_iters += sw4[1] + 1;
-          lloyd_dists += (int64_t)(sw4[1] + 1) * s_cur[w] * k;
-          ndeg[w] = sw4[2];
+          lloyd_iters += fin[j].iter + 1;
+          lloyd_dists += (int64_t)(fin[j].iter + 1) * s_cur[w] * k;
           rpass[bin_cur[w]] += 1;
-          if (sw4[0]) {
+          if (fin[j].accepted) {
+            fhat[w] = fin[j].f;
+            ndeg[w] = fin[j].ndeg;
             Lsum += s_cur[w];
             Lcount += 1;
             racc[bin_cur[w]] += 1;

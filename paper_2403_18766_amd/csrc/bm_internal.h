@@ -10,7 +10,6 @@
 namespace bm {
 
 constexpr int kWG = 256;         // threads per workgroup (4 wave64s)
-constexpr int kMaxTiles = 256;   // Lloyd tiles per job (bounds the partial-sum buffers)
 constexpr int kMaxRegDim = 64;   // largest padded dimension kept in registers
 constexpr int kDTile = 256;      // points per K-means++ tile
 
@@ -21,7 +20,7 @@ struct JobState {
   int32_t iter;    // centroid updates made so far
   int32_t active;  // 1 while the job still iterates
   int32_t ndeg;    // empty clusters under the final assignment
-  int32_t ntiles;  // Lloyd tiles of this job in the current launch geometry
+  int32_t accepted;// the run replaced the incumbent (Algorithm 1 acceptance)
   int32_t nchunks; // 256-point chunks of this job (objective partials)
   int32_t pad_;
 };
@@ -36,7 +35,7 @@ struct KppState {
   int32_t ntodo;     // degenerate centroids to fill
   int32_t has_d;     // D is defined (at least one centroid exists)
   int32_t step;      // next step number
-  int32_t pad_;
+  int32_t uniform;   // the pending pick is a uniform draw (no D^2 candidates)
 };
 
 // Arguments of the assignment kernels.  Job j reads its sample rows at
@@ -50,7 +49,6 @@ struct AssignArgs {
   int32_t cp;
   int32_t k;
   int32_t tile_pts;
-  int32_t max_tiles;
   int32_t max_chunks;
   int32_t vec;               // 1: rows are 16-byte aligned with ld == cp (vector loads)
   const int64_t* s;          // [job] sample sizes
@@ -64,25 +62,29 @@ struct AssignArgs {
   int64_t lab_stride;
   double* tf;                // [job][max_chunks] objective partial of each 256-point chunk
   int32_t* tnear;            // [job][max_chunks] near-tie count of each chunk (nullable)
-  unsigned long long* acc;   // [job][max_tiles][k][cp] fixed-point sums (Lloyd only)
-  int32_t* cnt;              // [job][max_tiles][k] cluster counts (Lloyd only)
+  unsigned long long* acc;   // [job][k][cp] fixed-point cluster sums (Lloyd only)
+  int32_t* cnt;              // [job][k] cluster counts (Lloyd only)
   const double* scale;       // [cp] fixed-point scales 2^shift_d
-  const JobState* st;        // nullable: jobs with active == 0 are skipped
+  const JobState* st;        // nullable: jobs with active == 0 are skipped; iter == 0 marks
+                             // the first assignment of a Lloyd run
 };
 
 struct FinalizeArgs {
-  int32_t n, cp, k, max_tiles, max_chunks, max_iter, kc, nchunks;
+  int32_t n, cp, k, max_chunks, max_iter;
   double tol;
-  const unsigned long long* acc;
-  const int32_t* cnt;
-  const double* tf;
-  const double* inv_scale;   // [cp] 2^-shift_d
+  const unsigned long long* acc;  // [job][k][cp]
+  const int32_t* cnt;             // [job][k]
+  const double* tf;               // [job][max_chunks]
+  const double* inv_scale;        // [cp] 2^-shift_d
   float* Cp;
   float* cn;
   JobState* st;
-  uint8_t* deg;              // [job][k], written when the job stops
-  int32_t* counter;          // [job] arrival counter (last workgroup commits)
-  int32_t* ndeg_acc;         // [job] empty-cluster count accumulated by the chunks
+  uint8_t* deg;                   // [job][k], written when the job stops
+  // Acceptance (optional, Cinc == nullptr skips it): when a job stops with
+  // f < fhat[job], its centroids, flags and f become the incumbent.
+  float* Cinc;                    // [job][k][n]
+  uint8_t* deg_inc;               // [job][k]
+  double* fhat;                   // [job]
 };
 
 // ---- launchers (bm_kernels.hip) ----
@@ -100,20 +102,17 @@ hipError_t launch_centroid_norms(hipStream_t st, const float* Cp, int32_t cp, in
                                  int32_t njobs, float* cn);
 hipError_t launch_assign(hipStream_t st, const AssignArgs& a, int32_t ntiles_total, bool sums);
 hipError_t launch_finalize(hipStream_t st, const FinalizeArgs& a, int32_t njobs);
-hipError_t launch_job_init(hipStream_t st, JobState* js, const int32_t* ntiles,
-                           const int64_t* sizes, int32_t njobs, int32_t* counter,
-                           int32_t* ndeg_acc);
+hipError_t launch_job_init(hipStream_t st, JobState* js, const int64_t* sizes, int32_t njobs,
+                           int32_t k, int32_t cp, unsigned long long* acc, int32_t* cnt,
+                           const float* Cp, float* cn);
 hipError_t launch_reduce_f(hipStream_t st, const double* tf, const int32_t* tnear,
                            const int64_t* sizes, int32_t max_chunks, int32_t njobs, double* f,
                            long long* near);
 hipError_t launch_unpad(hipStream_t st, const float* Cp, int32_t cp, int32_t n, int32_t k,
                         int32_t njobs, float* C, int64_t C_stride);
-hipError_t launch_accept(hipStream_t st, const float* Cp, int32_t cp, int32_t n, int32_t k,
-                         int32_t njobs, const JobState* js, const uint8_t* deg_work, float* Cinc,
-                         uint8_t* deg_inc, double* fhat, int32_t* status);
 hipError_t launch_copy_incumbent(hipStream_t st, const float* Cinc, const uint8_t* deg_inc,
                                  int32_t n, int32_t cp, int32_t k, int32_t njobs, float* Cp,
-                                 float* cn, uint8_t* deg_work);
+                                 uint8_t* deg_work);
 
 // K-means++ (greedy, batched over jobs)
 struct KppArgs {

@@ -15,8 +15,8 @@
 //
 // Numerics: the argmin runs on e_j = ||c_j||^2 - 2 x.c_j (one FMA per
 // dimension).  Its rounding error is bounded per point by
-// B = 2(2 gamma + 2u)(|x| cmax + cmax^2), gamma = (NP/4+2)u/(1-(NP/4+2)u),
-// u = 2^-24 (four interleaved partial sums).  A point whose two best e
+// B = 2(2 gamma + 2u)(|x| cmax + cmax^2), gamma = (NP/2+1)u/(1-(NP/2+1)u),
+// u = 2^-24 (two interleaved partial sums).  A point whose two best e
 // differ by more than 2B plus 2.5e-5 (e2 + |x|^2) keeps its winner; any other
 // point is decided again in the direct form sum_d (x_d - c_d)^2 over all
 // centres (lowest index on ties), which also counts the near ties
@@ -126,19 +126,6 @@ __device__ inline float dist_direct_reg(const float (&x)[NP], const float* __res
     p1 = fmaf(t1, t1, p1);
     p2 = fmaf(t2, t2, p2);
     p3 = fmaf(t3, t3, p3);
-  }
-  return (p0 + p1) + (p2 + p3);
-}
-
-template <int NP>
-__device__ inline float dot_reg(const float (&x)[NP], const float* __restrict__ c) {
-  float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
-#pragma unroll
-  for (int d = 0; d < NP; d += 4) {
-    p0 = fmaf(x[d], c[d], p0);
-    p1 = fmaf(x[d + 1], c[d + 1], p1);
-    p2 = fmaf(x[d + 2], c[d + 2], p2);
-    p3 = fmaf(x[d + 3], c[d + 3], p3);
   }
   return (p0 + p1) + (p2 + p3);
 }
@@ -276,148 +263,233 @@ __global__ __launch_bounds__(kWG) void k_unpad(const float* __restrict__ Cp, int
 }
 
 // ---------------------------------------------------------------------------
-// Assignment.  Grid = flattened tiles of all jobs; each workgroup handles
-// tile_pts points of one job in chunks of 256 (one point per lane).
+// Assignment.  Grid = flattened tiles of the active jobs; each workgroup
+// handles tile_pts points of one job in chunks of 256 (one point per lane).
+//
+// With SUMS (a Lloyd iteration) the per-cluster coordinate sums and counts
+// are maintained incrementally: only a point whose label changed since the
+// previous assignment of this Lloyd run contributes, +q to its new cluster
+// and -q to its old one, where q = x * 2^shift_d rounded to an integer.
+// The first assignment of a run counts every point.  The sums are exact
+// 64-bit integers, so the order of the atomic additions (LDS within the
+// workgroup, global across workgroups) cannot change the result.
 // ---------------------------------------------------------------------------
-template <int NP, bool SUMS>
+typedef const double __attribute__((address_space(4)))* cdouble_p;
+
+__device__ inline long long quantize(float x, double scale) {
+  return (long long)((double)x * scale);
+}
+
+// PPL points per lane: the workgroup covers 256*PPL consecutive points per
+// step, lane t taking points base + t + 256 p.  The job's centroids and norms
+// are first copied into LDS with one coalesced load (they were just written
+// by the previous kernel, so per-centroid fetches from memory would leave
+// every wave waiting on a chain of cache misses); the distance loop then
+// reads each centroid row as LDS broadcasts and feeds it to PPL*NP FMAs.
+template <int NP, int PPL, bool SUMS>
 __global__ __launch_bounds__(kWG) void k_assign_small(AssignArgs a) {
   const int job = a.tile_job[blockIdx.x];
   const int t = a.tile_idx[blockIdx.x];
-  if (a.st && !a.st[job].active) return;
+  int first_assign = 0;
+  if (a.st) {
+    const JobState st = a.st[job];
+    if (!st.active) return;
+    first_assign = st.iter == 0;
+  }
   const int64_t s = a.s[job];
   const int64_t p_begin = (int64_t)t * a.tile_pts;
   const int64_t p_end = min(s, p_begin + a.tile_pts);
   const float* __restrict__ S = a.S + job * a.S_stride;
-  const float* __restrict__ C = a.Cp + job * a.C_stride;
-  const float* __restrict__ cn = a.cn + job * a.cn_stride;
+  const float* __restrict__ Cg = a.Cp + job * a.C_stride;
+  const float* __restrict__ cng = a.cn + job * a.cn_stride;
+  const cdouble_p scale = (cdouble_p)a.scale;
+  int32_t* __restrict__ lab = a.labels ? a.labels + job * a.lab_stride : nullptr;
   const int k = a.k;
   const int n = a.n;
   const int ld = a.ld;
 
-  extern __shared__ unsigned long long lds_acc[];  // SUMS: [k][NP] sums, then [k] counts
-  unsigned int* lds_cnt = reinterpret_cast<unsigned int*>(lds_acc + (SUMS ? k * NP : 0));
+  // LDS: [k][NP] centroids, [k] norms, then (SUMS) [k][NP] int64 sums, [k] counts
+  extern __shared__ __align__(16) unsigned char smem[];
+  float* sC = reinterpret_cast<float*>(smem);
+  float* sCn = sC + k * NP;
+  unsigned long long* lds_acc =
+      reinterpret_cast<unsigned long long*>(smem + (((size_t)k * NP + k) * 4 + 15) / 16 * 16);
+  int* lds_cnt = reinterpret_cast<int*>(lds_acc + k * NP);
   __shared__ double red_f[4];
   __shared__ int red_i[4];
 
+  for (int e = threadIdx.x; e < k * NP / 4; e += kWG)
+    reinterpret_cast<float4*>(sC)[e] = reinterpret_cast<const float4*>(Cg)[e];
+  for (int e = threadIdx.x; e < k; e += kWG) sCn[e] = cng[e];
   if (SUMS) {
     for (int e = threadIdx.x; e < k * NP; e += kWG) lds_acc[e] = 0ull;
-    for (int e = threadIdx.x; e < k; e += kWG) lds_cnt[e] = 0u;
-    __syncthreads();
+    for (int e = threadIdx.x; e < k; e += kWG) lds_cnt[e] = 0;
   }
+  __syncthreads();
 
   float cmax2 = 0.f;
-  for (int j = 0; j < k; ++j) cmax2 = fmaxf(cmax2, cn[j]);
+  for (int j = 0; j < k; ++j) cmax2 = fmaxf(cmax2, sCn[j]);
   const float cmax = sqrtf(cmax2) * 1.0000002f;
-  constexpr float kTerms = (float)(NP / 4 + 2);
+  // two interleaved FMA chains of NP/2 terms per dot product, then one add
+  constexpr float kTerms = (float)(NP / 2 + 1);
   const float gam = kTerms * kU / (1.f - kTerms * kU);
   const float kB = 2.f * (2.f * gam + 2.f * kU);
   const bool vec = a.vec != 0;
 
-  for (int64_t base = p_begin; base < p_end; base += kWG) {
-    double fpart = 0.0;
-    int near = 0;
-    const int64_t i = base + threadIdx.x;
-    const bool valid = i < p_end;
-    float x[NP];
-    if (valid && vec) {
-      const float4* src = reinterpret_cast<const float4*>(S + i * (int64_t)NP);
+  int changed = 0;
+  for (int64_t base = p_begin; base < p_end; base += kWG * PPL) {
+    float x[PPL][NP];
+    bool valid[PPL];
+    int jold[PPL];
 #pragma unroll
-      for (int q = 0; q < NP / 4; ++q) {
-        const float4 v = src[q];
-        x[4 * q] = v.x;
-        x[4 * q + 1] = v.y;
-        x[4 * q + 2] = v.z;
-        x[4 * q + 3] = v.w;
+    for (int p = 0; p < PPL; ++p) {
+      const int64_t i = base + threadIdx.x + kWG * p;
+      valid[p] = i < p_end;
+      // previous label, loaded up front so its latency overlaps the distances
+      jold[p] = (SUMS && lab && valid[p] && !first_assign) ? lab[i] : -1;
+      if (valid[p] && vec) {
+        const float4* src = reinterpret_cast<const float4*>(S + i * (int64_t)NP);
+#pragma unroll
+        for (int q = 0; q < NP / 4; ++q) {
+          const float4 v = src[q];
+          x[p][4 * q] = v.x;
+          x[p][4 * q + 1] = v.y;
+          x[p][4 * q + 2] = v.z;
+          x[p][4 * q + 3] = v.w;
+        }
+      } else {
+#pragma unroll
+        for (int d = 0; d < NP; ++d) x[p][d] = (valid[p] && d < n) ? S[i * (int64_t)ld + d] : 0.f;
       }
-    } else {
-#pragma unroll
-      for (int d = 0; d < NP; ++d) x[d] = (valid && d < n) ? S[i * (int64_t)ld + d] : 0.f;
     }
 
-    // best and second-best expanded-form values
-    float e1 = __builtin_inff(), e2 = __builtin_inff();
-    int j1 = 0;
-    for (int j = 0; j < k; ++j) {
-      const float e = fmaf(-2.f, dot_reg<NP>(x, C + j * NP), cn[j]);
-      const bool better = e < e1;
-      e2 = better ? e1 : fminf(e2, e);
-      j1 = better ? j : j1;
-      e1 = better ? e : e1;
-    }
-    float xx = 0.f;
+    // best and second-best expanded-form values e_j = ||c_j||^2 - 2 x.c_j
+    float e1[PPL], e2[PPL];
+    int j1[PPL];
 #pragma unroll
-    for (int d = 0; d < NP; ++d) xx = fmaf(x[d], x[d], xx);
-    const float B = kB * (sqrtf(xx) * cmax + cmax2);
-    const bool recheck = valid && !((e2 - e1) > 2.f * B + 2.5e-5f * fabsf(e2 + xx));
-    if (recheck) {
-      float b1 = __builtin_inff(), b2 = __builtin_inff();
-      int jb = 0;
-      for (int j = 0; j < k; ++j) {
-        const float dd = dist_direct_reg<NP>(x, C + j * NP);
-        if (dd < b1) {
-          b2 = b1;
-          b1 = dd;
-          jb = j;
-        } else if (dd < b2) {
-          b2 = dd;
+    for (int p = 0; p < PPL; ++p) {
+      e1[p] = __builtin_inff();
+      e2[p] = __builtin_inff();
+      j1[p] = 0;
+    }
+    for (int j = 0; j < k; ++j) {
+      const float4* c4 = reinterpret_cast<const float4*>(sC + j * NP);
+      float q0[PPL], q1[PPL];
+#pragma unroll
+      for (int p = 0; p < PPL; ++p) q0[p] = q1[p] = 0.f;
+#pragma unroll
+      for (int q = 0; q < NP / 4; ++q) {
+        const float4 c = c4[q];
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) {
+          q0[p] = fmaf(x[p][4 * q], c.x, q0[p]);
+          q1[p] = fmaf(x[p][4 * q + 1], c.y, q1[p]);
+          q0[p] = fmaf(x[p][4 * q + 2], c.z, q0[p]);
+          q1[p] = fmaf(x[p][4 * q + 3], c.w, q1[p]);
         }
       }
-      j1 = jb;
-      if (b2 - b1 < 1e-5f * b2) ++near;
-    }
-    if (valid) {
-      const float d1 = dist_direct_reg<NP>(x, C + j1 * NP);
-      fpart += (double)d1;
-      if (a.labels) a.labels[job * a.lab_stride + i] = j1;
-      if (SUMS) {
+      const float cnj = sCn[j];
 #pragma unroll
-        for (int d = 0; d < NP; ++d) {
-          if (d < n) {
-            const long long q = __double2ll_rn((double)x[d] * a.scale[d]);
-            atomicAdd(&lds_acc[j1 * NP + d], (unsigned long long)q);
+      for (int p = 0; p < PPL; ++p) {
+        const float e = fmaf(-2.f, q0[p] + q1[p], cnj);
+        // new second best is the median of (best, e, second best)
+        e2[p] = __builtin_amdgcn_fmed3f(e1[p], e, e2[p]);
+        j1[p] = e < e1[p] ? j : j1[p];
+        e1[p] = fminf(e1[p], e);
+      }
+    }
+
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) {
+      double fpart = 0.0;
+      int near = 0;
+      const int64_t i = base + threadIdx.x + kWG * p;
+      float xx = 0.f;
+#pragma unroll
+      for (int d = 0; d < NP; ++d) xx = fmaf(x[p][d], x[p][d], xx);
+      const float B = kB * (sqrtf(xx) * cmax + cmax2);
+      const bool recheck = valid[p] && !((e2[p] - e1[p]) > 2.f * B + 2.5e-5f * fabsf(e2[p] + xx));
+      int jw = j1[p];
+      if (recheck) {
+        float b1 = __builtin_inff(), b2 = __builtin_inff();
+        int jb = 0;
+        for (int j = 0; j < k; ++j) {
+          const float dd = dist_direct_reg<NP>(x[p], sC + j * NP);
+          if (dd < b1) {
+            b2 = b1;
+            b1 = dd;
+            jb = j;
+          } else if (dd < b2) {
+            b2 = dd;
           }
         }
-        atomicAdd(&lds_cnt[j1], 1u);
+        jw = jb;
+        if (b2 - b1 < 1e-5f * b2) ++near;
       }
-    }
-    // objective and near-tie count of this 256-point chunk
-    const double ft = block_sum_f64(fpart, red_f);
-    const int nt = block_sum_i32(near, red_i);
-    if (threadIdx.x == 0) {
-      const int64_t ch = (int64_t)job * a.max_chunks + base / kWG;
-      a.tf[ch] = ft;
-      if (a.tnear) a.tnear[ch] = nt;
+      if (valid[p]) {
+        // the winner's distance in the direct form
+        const float d1 = dist_direct_reg<NP>(x[p], sC + jw * NP);
+        fpart += (double)d1;
+        const int jo = jold[p];
+        if (lab) lab[i] = jw;
+        if (SUMS && jo != jw) {
+          changed = 1;
+#pragma unroll
+          for (int d = 0; d < NP; ++d) {
+            if (d < n) {
+              const long long q = quantize(x[p][d], scale[d]);
+              atomicAdd(&lds_acc[jw * NP + d], (unsigned long long)q);
+              if (jo >= 0) atomicAdd(&lds_acc[jo * NP + d], (unsigned long long)(-q));
+            }
+          }
+          atomicAdd(&lds_cnt[jw], 1);
+          if (jo >= 0) atomicAdd(&lds_cnt[jo], -1);
+        }
+      }
+      // objective and near-tie count of this 256-point chunk
+      const double ft = block_sum_f64(fpart, red_f);
+      const int nt = block_sum_i32(near, red_i);
+      const int64_t cbase = base + kWG * p;
+      if (threadIdx.x == 0 && cbase < p_end) {
+        const int64_t ch = (int64_t)job * a.max_chunks + cbase / kWG;
+        a.tf[ch] = ft;
+        if (a.tnear) a.tnear[ch] = nt;
+      }
     }
   }
 
   if (SUMS) {
-    // block_sum_* ended with a barrier, so the LDS sums are complete
-    const int64_t slot = (int64_t)job * a.max_tiles + t;
-    unsigned long long* dst = a.acc + slot * (int64_t)k * NP;
-    for (int e = threadIdx.x; e < k * NP; e += kWG) dst[e] = lds_acc[e];
-    int32_t* cdst = a.cnt + slot * k;
-    for (int e = threadIdx.x; e < k; e += kWG) cdst[e] = (int32_t)lds_cnt[e];
+    const int any = __syncthreads_or(changed);
+    if (any) {
+      unsigned long long* dst = a.acc + (int64_t)job * k * NP;
+      for (int e = threadIdx.x; e < k * NP; e += kWG) {
+        const unsigned long long v = lds_acc[e];
+        if (v) atomicAdd(&dst[e], v);
+      }
+      int32_t* cdst = a.cnt + (int64_t)job * k;
+      for (int e = threadIdx.x; e < k; e += kWG) {
+        const int v = lds_cnt[e];
+        if (v) atomicAdd(&cdst[e], v);
+      }
+    }
   }
 }
 
 // ---------------------------------------------------------------------------
-// Lloyd finalize.  Grid (nchunks, jobs); chunk c owns centroids
-// [c*kc, (c+1)*kc) with one thread per (centroid, padded dimension).
-// Every workgroup of a job computes the same f (fixed-order tile sum) and the
-// same decision; the last workgroup to arrive commits the job state.
+// Lloyd finalize: one workgroup per job.  f = fixed-order sum of the chunk
+// partials; stop (f_prev - f <= tol f, f not finite, or max_iter updates) or
+// move every non-empty centroid to fp32(sum / count) and recompute its norm.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kWG) void k_finalize(FinalizeArgs a) {
-  const int job = blockIdx.y;
-  const int chunk = blockIdx.x;
+  const int job = blockIdx.x;
   JobState st = a.st[job];
   if (!st.active) return;
-  const int nt = st.ntiles;
   const int k = a.k, cp = a.cp;
   __shared__ double sh_f;
   __shared__ int sh_upd;
-  __shared__ int sh_cnt[kWG];
-  __shared__ double sh_sq[kWG];
-  __shared__ int sh_last;
+  __shared__ int sh_acc;
+  __shared__ int sh_empty;
+  extern __shared__ double sh_sq[];  // [k][cp]
   if (threadIdx.x < 64) {
     const double f = wave_chunked_sum(a.tf + (int64_t)job * a.max_chunks, st.nchunks);
     const bool stop = (st.iter > 0 && st.f_prev - f <= a.tol * f) || !isfinite(f) ||
@@ -425,89 +497,96 @@ __global__ __launch_bounds__(kWG) void k_finalize(FinalizeArgs a) {
     if (threadIdx.x == 0) {
       sh_f = f;
       sh_upd = stop ? 0 : 1;
+      // Acceptance (Algorithm 1): the run replaces the incumbent only if its
+      // objective is strictly smaller (a NaN never is).
+      sh_acc = (stop && a.Cinc != nullptr && f < a.fhat[job]) ? 1 : 0;
+      sh_empty = 0;
     }
   }
   __syncthreads();
   const int upd = sh_upd;
-  const int jj = threadIdx.x / cp;
-  const int d = threadIdx.x - jj * cp;
-  const int j = chunk * a.kc + jj;
-  const bool mine = jj < a.kc && j < k;
-  int cntj = 0;
-  if (mine && d == 0) {
-    for (int t = 0; t < nt; ++t) cntj += a.cnt[((int64_t)job * a.max_tiles + t) * k + j];
-    sh_cnt[jj] = cntj;
-  }
-  __syncthreads();
-  double sq = 0.0;
-  if (mine) {
-    cntj = sh_cnt[jj];
-    float* c = a.Cp + ((int64_t)job * k + j) * cp + d;
-    if (upd) {
-      if (cntj > 0) {
-        unsigned long long sum = 0ull;
-        for (int t = 0; t < nt; ++t)
-          sum += a.acc[(((int64_t)job * a.max_tiles + t) * k + j) * cp + d];
-        const double mean = ((double)(long long)sum * a.inv_scale[d]) / (double)cntj;
-        *c = (float)mean;
+  const unsigned long long* acc = a.acc + (int64_t)job * k * cp;
+  const int32_t* cnt = a.cnt + (int64_t)job * k;
+  float* C = a.Cp + (int64_t)job * k * cp;
+  if (upd) {
+    for (int e = threadIdx.x; e < k * cp; e += kWG) {
+      const int j = e / cp, d = e - j * cp;
+      const int cj = cnt[j];
+      if (cj > 0) {
+        const double mean = ((double)(long long)acc[e] * a.inv_scale[d]) / (double)cj;
+        C[e] = (float)mean;
       }
-      const double cv = *c;
-      sq = cv * cv;
-    } else if (d == 0) {
-      a.deg[(int64_t)job * k + j] = cntj == 0 ? 1 : 0;
+      const double cv = C[e];
+      sh_sq[e] = cv * cv;
     }
-  }
-  sh_sq[threadIdx.x] = sq;
-  __syncthreads();
-  if (upd && mine && d == 0) {
-    double acc = 0.0;
-    for (int q = 0; q < cp; ++q) acc += sh_sq[jj * cp + q];
-    a.cn[(int64_t)job * k + j] = (float)acc;
-  }
-  if (!upd && threadIdx.x == 0) {
+    __syncthreads();
+    for (int j = threadIdx.x; j < k; j += kWG) {
+      double q = 0.0;
+      for (int d = 0; d < cp; ++d) q += sh_sq[j * cp + d];
+      a.cn[(int64_t)job * k + j] = (float)q;
+    }
+  } else {
     int empty = 0;
-    for (int q = 0; q < a.kc && chunk * a.kc + q < k; ++q) empty += sh_cnt[q] == 0 ? 1 : 0;
-    if (empty) atomicAdd(&a.ndeg_acc[job], empty);
+    for (int j = threadIdx.x; j < k; j += kWG) {
+      const int e0 = cnt[j] == 0 ? 1 : 0;
+      a.deg[(int64_t)job * k + j] = (uint8_t)e0;
+      empty += e0;
+    }
+    if (empty) atomicAdd(&sh_empty, empty);
   }
-  __threadfence();
   __syncthreads();
+  const bool accept = sh_acc != 0;
+  if (accept) {
+    const int n = a.n;
+    for (int e = threadIdx.x; e < k * n; e += kWG) {
+      const int j = e / n, d = e - j * n;
+      a.Cinc[(int64_t)job * k * n + e] = C[j * cp + d];
+    }
+    for (int j = threadIdx.x; j < k; j += kWG)
+      a.deg_inc[(int64_t)job * k + j] = a.deg[(int64_t)job * k + j];
+  }
   if (threadIdx.x == 0) {
-    const int prev = atomicAdd(&a.counter[job], 1);
-    sh_last = (prev == a.nchunks - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  if (sh_last && threadIdx.x == 0) {
-    __threadfence();
-    a.counter[job] = 0;
     st.f = sh_f;
     if (upd) {
       st.f_prev = sh_f;
       st.iter += 1;
     } else {
       st.active = 0;
-      st.ndeg = atomicAdd(&a.ndeg_acc[job], 0);
-      a.ndeg_acc[job] = 0;
+      st.ndeg = sh_empty;
+      st.accepted = accept ? 1 : 0;
+      if (accept) a.fhat[job] = sh_f;
     }
     a.st[job] = st;
   }
 }
 
-__global__ void k_job_init(JobState* js, const int32_t* ntiles, const int64_t* sizes, int njobs,
-                           int32_t* counter, int32_t* ndeg_acc) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= njobs) return;
-  JobState st;
-  st.f = 0.0;
-  st.f_prev = 0.0;
-  st.iter = 0;
-  st.active = 1;
-  st.ndeg = 0;
-  st.ntiles = ntiles[j];
-  st.nchunks = (int32_t)((sizes[j] + kWG - 1) / kWG);
-  st.pad_ = 0;
-  js[j] = st;
-  counter[j] = 0;
-  ndeg_acc[j] = 0;
+// Start of a Lloyd run: job state, zero cluster sums and counts, and the
+// norms ||c_j||^2 (FP64, rounded once) of the starting centroids.
+__global__ __launch_bounds__(kWG) void k_job_init(JobState* js, const int64_t* sizes, int k, int cp,
+                                                  unsigned long long* acc, int32_t* cnt,
+                                                  const float* __restrict__ Cp,
+                                                  float* __restrict__ cn) {
+  const int j = blockIdx.x;
+  for (int e = threadIdx.x; e < k * cp; e += kWG) acc[(int64_t)j * k * cp + e] = 0ull;
+  for (int e = threadIdx.x; e < k; e += kWG) cnt[(int64_t)j * k + e] = 0;
+  for (int r = threadIdx.x; r < k; r += kWG) {
+    const float* c = Cp + ((int64_t)j * k + r) * cp;
+    double q = 0.0;
+    for (int d = 0; d < cp; ++d) q += (double)c[d] * (double)c[d];
+    cn[(int64_t)j * k + r] = (float)q;
+  }
+  if (threadIdx.x == 0) {
+    JobState st;
+    st.f = 0.0;
+    st.f_prev = 0.0;
+    st.iter = 0;
+    st.active = 1;
+    st.ndeg = 0;
+    st.accepted = 0;
+    st.nchunks = (int32_t)((sizes[j] + kWG - 1) / kWG);
+    st.pad_ = 0;
+    js[j] = st;
+  }
 }
 
 // Objective of each job: fixed-order sum of its chunk partials (one wave per job).
@@ -531,47 +610,11 @@ __global__ __launch_bounds__(64) void k_reduce_f(const double* __restrict__ tf,
   }
 }
 
-// Acceptance (Algorithm 1): replace the incumbent only if f_new < f_hat
-// (strict; a NaN never passes).  status[job] = {accepted, updates, ndeg}.
-__global__ __launch_bounds__(kWG) void k_accept(const float* __restrict__ Cp, int cp, int n, int k,
-                                                const JobState* __restrict__ js,
-                                                const uint8_t* __restrict__ deg_work,
-                                                float* __restrict__ Cinc,
-                                                uint8_t* __restrict__ deg_inc,
-                                                double* __restrict__ fhat,
-                                                int32_t* __restrict__ status) {
-  const int job = blockIdx.x;
-  const JobState st = js[job];
-  const double fh = fhat[job];
-  const bool acc = st.f < fh;
-  __syncthreads();
-  if (acc) {
-    for (int e = threadIdx.x; e < k * n; e += kWG) {
-      const int r = e / n, d = e - r * n;
-      Cinc[(int64_t)job * k * n + e] = Cp[((int64_t)job * k + r) * cp + d];
-    }
-    for (int e = threadIdx.x; e < k; e += kWG) deg_inc[(int64_t)job * k + e] = deg_work[(int64_t)job * k + e];
-  }
-  __syncthreads();
-  __shared__ int red[4];
-  int nd = 0;
-  for (int e = threadIdx.x; e < k; e += kWG) nd += deg_inc[(int64_t)job * k + e] ? 1 : 0;
-  nd = block_sum_i32(nd, red);
-  if (threadIdx.x == 0) {
-    if (acc) fhat[job] = st.f;
-    status[job * 4 + 0] = acc ? 1 : 0;
-    status[job * 4 + 1] = st.iter;
-    status[job * 4 + 2] = nd;
-    status[job * 4 + 3] = 0;
-  }
-}
-
 // Start of a pass: working centroids and degenerate flags from the incumbent.
 __global__ __launch_bounds__(kWG) void k_copy_incumbent(const float* __restrict__ Cinc,
                                                          const uint8_t* __restrict__ deg_inc,
                                                          int n, int cp, int k,
                                                          float* __restrict__ Cp,
-                                                         float* __restrict__ cn,
                                                          uint8_t* __restrict__ deg_work) {
   const int job = blockIdx.x;
   for (int e = threadIdx.x; e < k * cp; e += kWG) {
@@ -579,14 +622,6 @@ __global__ __launch_bounds__(kWG) void k_copy_incumbent(const float* __restrict_
     Cp[(int64_t)job * k * cp + e] = d < n ? Cinc[((int64_t)job * k + r) * n + d] : 0.f;
   }
   for (int e = threadIdx.x; e < k; e += kWG) deg_work[(int64_t)job * k + e] = deg_inc[(int64_t)job * k + e];
-  for (int r = threadIdx.x; r < k; r += kWG) {
-    double acc = 0.0;
-    for (int d = 0; d < n; ++d) {
-      const double v = Cinc[((int64_t)job * k + r) * n + d];
-      acc += v * v;
-    }
-    cn[(int64_t)job * k + r] = (float)acc;
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -615,7 +650,7 @@ __global__ __launch_bounds__(kWG) void k_kpp_setup(KppArgs a) {
     ks.ntodo = nt;
     ks.has_d = nt < k ? 1 : 0;
     ks.step = 0;
-    ks.pad_ = 0;
+    ks.uniform = 0;
     a.ks[job] = ks;
   }
 }
@@ -719,7 +754,7 @@ __global__ __launch_bounds__(64) void k_kpp_step(KppArgs a) {
       if (a.picks) {
         int32_t* p = a.picks + ((int64_t)job * k + j) * 4;
         p[0] = (int32_t)istar;
-        for (int c = 0; c < 3; ++c) p[1 + c] = (ks.ncand > 1 && c < ks.ncand) ? ks.cand[c] : -1;
+        for (int c = 0; c < 3; ++c) p[1 + c] = (!ks.uniform && c < ks.ncand) ? ks.cand[c] : -1;
       }
     }
     ks.dcur = other_slot(ks.dcur, best);
@@ -735,10 +770,12 @@ __global__ __launch_bounds__(64) void k_kpp_step(KppArgs a) {
     if (ks.has_d && ks.step == 0) ks.T = wave_prefix_search<double>(dt, ndt, -1.0, nullptr, nullptr);
     if (!ks.has_d || !(ks.T > 0.0 && ks.T < __builtin_inf())) {
       ks.ncand = 1;
+      ks.uniform = 1;
       ks.cand[0] = (int32_t)bounded(w.w[3], (uint64_t)s);
       ks.cand[1] = ks.cand[2] = -1;
     } else {
       ks.ncand = a.n_cand;
+      ks.uniform = 0;
       const float* Dj = a.D + (int64_t)ks.dcur * a.D_slot_stride + job * a.D_job_stride;
       for (int c = 0; c < a.n_cand; ++c) {
         const double tau = u01(w.w[c]) * ks.T;
@@ -799,16 +836,25 @@ __global__ __launch_bounds__(kWG) void k_kpp_pot(KppArgs a) {
 
 template <int NP>
 hipError_t launch_assign_np(hipStream_t st, const AssignArgs& a, int ntiles, bool sums) {
+  // two points per lane while both fit comfortably in registers
+  constexpr int PPL = NP <= 32 ? 2 : 1;
+  const size_t base = (((size_t)a.k * NP + a.k) * 4 + 15) / 16 * 16;
   if (sums) {
-    const size_t lds = (size_t)a.k * NP * 8 + (size_t)a.k * 4;
+    const size_t lds = base + (size_t)a.k * NP * 8 + (size_t)a.k * 4;
     if (lds > 64 * 1024) {
-      hipError_t e = hipFuncSetAttribute((const void*)k_assign_small<NP, true>,
+      hipError_t e = hipFuncSetAttribute((const void*)k_assign_small<NP, PPL, true>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_assign_small<NP, true>), dim3(ntiles), dim3(kWG), lds, st, a);
+    hipLaunchKernelGGL((k_assign_small<NP, PPL, true>), dim3(ntiles), dim3(kWG), lds, st, a);
   } else {
-    hipLaunchKernelGGL((k_assign_small<NP, false>), dim3(ntiles), dim3(kWG), 0, st, a);
+    const size_t lds = base;
+    if (lds > 64 * 1024) {
+      hipError_t e = hipFuncSetAttribute((const void*)k_assign_small<NP, PPL, false>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_assign_small<NP, PPL, false>), dim3(ntiles), dim3(kWG), lds, st, a);
   }
   return hipGetLastError();
 }
@@ -893,15 +939,21 @@ hipError_t launch_assign(hipStream_t st, const AssignArgs& a, int32_t ntiles, bo
 }
 
 hipError_t launch_finalize(hipStream_t st, const FinalizeArgs& a, int32_t njobs) {
-  hipLaunchKernelGGL(k_finalize, dim3(a.nchunks, njobs), dim3(kWG), 0, st, a);
+  const size_t lds = (size_t)a.k * a.cp * sizeof(double);
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_finalize,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_finalize, dim3(njobs), dim3(kWG), lds, st, a);
   return hipGetLastError();
 }
 
-hipError_t launch_job_init(hipStream_t st, JobState* js, const int32_t* ntiles,
-                           const int64_t* sizes, int32_t njobs, int32_t* counter,
-                           int32_t* ndeg_acc) {
-  hipLaunchKernelGGL(k_job_init, dim3((njobs + 63) / 64), dim3(64), 0, st, js, ntiles, sizes,
-                     njobs, counter, ndeg_acc);
+hipError_t launch_job_init(hipStream_t st, JobState* js, const int64_t* sizes, int32_t njobs,
+                           int32_t k, int32_t cp, unsigned long long* acc, int32_t* cnt,
+                           const float* Cp, float* cn) {
+  hipLaunchKernelGGL(k_job_init, dim3(njobs), dim3(kWG), 0, st, js, sizes, k, cp, acc, cnt, Cp,
+                     cn);
   return hipGetLastError();
 }
 
@@ -919,19 +971,11 @@ hipError_t launch_unpad(hipStream_t st, const float* Cp, int32_t cp, int32_t n, 
   return hipGetLastError();
 }
 
-hipError_t launch_accept(hipStream_t st, const float* Cp, int32_t cp, int32_t n, int32_t k,
-                         int32_t njobs, const JobState* js, const uint8_t* deg_work, float* Cinc,
-                         uint8_t* deg_inc, double* fhat, int32_t* status) {
-  hipLaunchKernelGGL(k_accept, dim3(njobs), dim3(kWG), 0, st, Cp, cp, n, k, js, deg_work, Cinc,
-                     deg_inc, fhat, status);
-  return hipGetLastError();
-}
-
 hipError_t launch_copy_incumbent(hipStream_t st, const float* Cinc, const uint8_t* deg_inc,
                                  int32_t n, int32_t cp, int32_t k, int32_t njobs, float* Cp,
-                                 float* cn, uint8_t* deg_work) {
+                                 uint8_t* deg_work) {
   hipLaunchKernelGGL(k_copy_incumbent, dim3(njobs), dim3(kWG), 0, st, Cinc, deg_inc, n, cp, k, Cp,
-                     cn, deg_work);
+                     deg_work);
   return hipGetLastError();
 }
 
