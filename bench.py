@@ -79,8 +79,9 @@ def main():
     ap.add_argument("--cpu-workers", type=int, default=16)
     ap.add_argument("--cpu-passes", type=int, default=10)
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-target run")
-    ap.add_argument("--plain", action="store_true",
-                    help="one worker's sample per launch instead of all workers together")
+    ap.add_argument("--mode", type=int, default=1,
+                    help="1 persistent rounds (default), 2 one launch per Lloyd step, "
+                         "0 one worker's sample per launch")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -102,7 +103,7 @@ def main():
     P = api.RunParams(k=WORKLOAD["k"], workers=WORKLOAD["workers"], rounds_T=WORKLOAD["rounds_T"],
                       passes_p=WORKLOAD["passes_p"], s_min=WORKLOAD["s_min"],
                       s_max=WORKLOAD["s_max"], size_policy=_lib.BM_SIZE_LOGUNIFORM, seed=0,
-                      batched=not args.plain)
+                      batched=args.mode)
     api.reserve(dev, WORKLOAD["s_max"], n, WORKLOAD["k"], WORKLOAD["workers"])
     for w in range(args.warmup):
         log("warmup", w)
@@ -127,7 +128,9 @@ def main():
     lloyd_sec = sum(r["lloyd_seconds"] for r in results)
     flops = st["assign_dists"] * 2.0 * n
     achieved = flops / st["assign_seconds"] / 1e12 if st["assign_seconds"] > 0 else 0.0
-    roof = {"bound": "alu", "kernel": "k_assign_small<28,true> (Lloyd assignment + partial update)",
+    kname = ("k_round<28> (persistent round: sampling, K-means++, Lloyd, acceptance)"
+             if args.mode == 1 else "k_assign_small<28,2,true> (Lloyd assignment + update)")
+    roof = {"bound": "alu", "kernel": kname,
             "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
             "avg_launch_us": 1e6 * st["assign_seconds"] / max(1, st["assign_launches"]),
@@ -159,7 +162,8 @@ def main():
                                "T=5 rounds x p=10 passes, Lloyd <=300 iters tol 1e-4, "
                                "3 K-means++ candidates",
                    "m": m, "n": n, "k": WORKLOAD["k"], "workers": WORKLOAD["workers"],
-                   "batched": not args.plain},
+                   "mode": {1: "persistent rounds", 2: "one launch per Lloyd step",
+                            0: "one worker per launch"}[args.mode]},
         "roofline": roof,
         "cpu_baseline": cpu,
         "lloyd_phase_dists_per_s": dists / lloyd_sec if lloyd_sec > 0 else None,

@@ -183,8 +183,11 @@ typedef struct bm_params {
   int32_t n_candidates;/* K-means++ candidates (Section 5: 3) */
   int32_t size_policy; /* bm_size_policy */
   int32_t prec;        /* BM_FP32 */
-  int32_t batched;     /* 1: run all workers' passes together (default);
-                          0: one worker's sample per launch (reference plain path) */
+  int32_t batched;     /* 1: one persistent cooperative launch per round, each worker on
+                             its own group of workgroups (default);
+                          2: all workers' passes together, one launch per Lloyd step;
+                          0: one worker's sample per launch (reference plain path).
+                          All three give bitwise identical results. */
   double tol;          /* Lloyd relative tolerance (Section 5: 1e-4) */
   uint64_t seed;
 } bm_params;

@@ -154,14 +154,14 @@ class RunParams:
     n_candidates: int = 3
     size_policy: int = BM_SIZE_UNIFORM
     seed: int = 0
-    batched: bool = True
+    batched: int = 1   # 1 persistent rounds, 2 one launch per Lloyd step, 0 one worker per launch
 
     def c_struct(self, m, n):
         return _CParams(m=int(m), s_min=int(self.s_min), s_max=int(self.s_max), n=int(n),
                         k=int(self.k), workers=int(self.workers), rounds_T=int(self.rounds_T),
                         passes_p=int(self.passes_p), max_iter=int(self.max_iter),
                         n_candidates=int(self.n_candidates), size_policy=int(self.size_policy),
-                        prec=BM_FP32, batched=1 if self.batched else 0, tol=float(self.tol),
+                        prec=BM_FP32, batched=int(self.batched), tol=float(self.tol),
                         seed=int(self.seed))
 
 

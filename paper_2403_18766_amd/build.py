@@ -13,6 +13,9 @@ HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-fvisibility=hidden",
     # packed FP32 VALU instructions stay off (plain v_fma_f32 / v_add_f32)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # workgroups of one persistent launch exchange data through global memory;
+    # keep global loads on the coherent vector path (no scalar-cache reuse)
+    "-mllvm", "-amdgpu-scalarize-global-loads=false",
 ]
 
 

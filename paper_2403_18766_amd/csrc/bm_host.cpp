@@ -55,7 +55,10 @@ struct bm_ctx {
 
   // device workspace
   DevBuf S, idx, labels, Cp, cn, Cinc, deg_work, deg_inc, fhat, acc, cnt, tf, tnear, js, sizes, tile_job, tile_idx, rkeys, seed_worker, absmax, scale, inv_scale,
-      fjob, nearjob, D, Dt, ks, todo, picks;
+      fjob, nearjob, D, Dt, ks, todo, picks, gs, rflags, wgmap, rargs, rres, bars, rwork;
+  int xcd_cap = 0;                  // grid size the XCD layout below was measured for
+  int xcd_wgs[bm::kMaxXcd] = {0};   // workgroups of that grid on each XCD
+  bool round_ok = true;             // the persistent round kernel fits this device
   int64_t tile_cap = 0;  // entries of tile_job / tile_idx
 
   // pinned staging ring
@@ -205,6 +208,10 @@ int reserve_impl(bm_ctx* c, int64_t max_s, int max_n, int max_k, int max_jobs) {
   BM_TRY(dev_alloc(c, c->ks, J * sizeof(KppState)));
   BM_TRY(dev_alloc(c, c->todo, J * max_k * sizeof(int32_t)));
   BM_TRY(dev_alloc(c, c->picks, J * max_k * 4 * sizeof(int32_t)));
+  BM_TRY(dev_alloc(c, c->gs, J * sizeof(uint64_t)));
+  BM_TRY(dev_alloc(c, c->rflags, J * sizeof(int32_t)));
+  BM_TRY(dev_alloc(c, c->bars, J * sizeof(bm::GroupBar)));
+  BM_TRY(dev_alloc(c, c->rargs, sizeof(bm::RoundArgs)));
   c->max_s = max_s;
   c->max_n = max_n;
   c->max_k = max_k;
@@ -528,6 +535,202 @@ int kpp_batch(bm_ctx* c, const BatchView& b, const KppBatch& kb) {
   return BM_OK;
 }
 
+// One round of Algorithm 1 for all workers in a single cooperative launch of
+// the persistent round kernel: workgroups are split among the workers in
+// proportion to their sample sizes; each worker runs its re-evaluation (if
+// its size changed) and its passes on its own group.  Fills, per worker, the
+// re-evaluated f (recalc_f) and the per-pass results (out[w * p + q]).
+struct RoundResult {
+  std::vector<double> recalc_f;
+  std::vector<bm::PassOut> out;
+  double seconds = 0.0;
+};
+
+// Returned by round_persistent when the device's workgroup placement does not
+// fit the worker layout; nothing ran and the round goes to the multi-launch path.
+constexpr int kRoundNoFit = 1;
+
+// Workgroups per XCD of a co-resident grid of `cap` workgroups (measured once).
+int xcd_layout(bm_ctx* c, int cap) {
+  if (c->xcd_cap == cap) return BM_OK;
+  DevBuf tmp;
+  BM_TRY(dev_alloc(c, tmp, (size_t)cap * sizeof(uint32_t)));
+  hipError_t e = bm::launch_xcd_probe(c->stream, P<uint32_t>(tmp), cap);
+  std::vector<uint32_t> ids(cap);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ids.data(), tmp.p, (size_t)cap * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                       c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  dev_free(tmp);
+  if (e != hipSuccess) return c->fail(BM_E_HIP, "XCD probe: %s", hipGetErrorString(e));
+  for (int x = 0; x < bm::kMaxXcd; ++x) c->xcd_wgs[x] = 0;
+  for (uint32_t v : ids) c->xcd_wgs[v % bm::kMaxXcd] += 1;
+  c->xcd_cap = cap;
+  return BM_OK;
+}
+
+// One round of Algorithm 1 for all workers in one cooperative launch.  Workers
+// are placed on XCDs largest first, each on the XCD whose load per workgroup
+// grows least (at most one worker per workgroup of an XCD).
+int round_persistent(bm_ctx* c, const float* X, const bm_params& p, int t,
+                     const std::vector<int64_t>& sizes, const std::vector<int32_t>& recalc,
+                     RoundResult* res) {
+  const int W = p.workers, k = p.k, n = p.n, cp = round_up4(n);
+  const size_t lds = bm::round_lds_bytes(cp, k);
+  int cap = 0;
+  HIP_TRY(c, bm::round_capacity(cp, lds, &cap));
+  if (cap < W) return kRoundNoFit;
+  BM_TRY(xcd_layout(c, cap));
+  std::vector<int> order(W);
+  for (int w = 0; w < W; ++w) order[w] = w;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return sizes[a] > sizes[b]; });
+  std::vector<int32_t> xnw(bm::kMaxXcd, 0), xw((size_t)bm::kMaxXcd * W, 0);
+  std::vector<double> load(bm::kMaxXcd, 0.0);
+  for (int w : order) {
+    const double ch = (double)((sizes[w] + bm::kWG - 1) / bm::kWG);
+    int best = -1;
+    double best_v = 0.0;
+    for (int x = 0; x < bm::kMaxXcd; ++x) {
+      if (xnw[x] >= c->xcd_wgs[x]) continue;
+      const double v = (load[x] + ch) / (double)c->xcd_wgs[x];
+      if (best < 0 || v < best_v) {
+        best = x;
+        best_v = v;
+      }
+    }
+    if (best < 0) return kRoundNoFit;
+    xw[(size_t)best * W + xnw[best]] = w;
+    xnw[best] += 1;
+    load[best] += ch;
+  }
+  const int64_t mc = c->max_chunks;
+  // work buffer: [reg kMaxXcd][grid barrier][W barriers][delta W*3*k*cp][dcnt W*3*k] | [tf3 W*3*mc]
+  const size_t off_gbar = 64, off_bar = 128;
+  const size_t off_delta = off_bar + (size_t)W * sizeof(bm::GroupBar);
+  const size_t off_dcnt = off_delta + (size_t)W * 3 * k * cp * sizeof(unsigned long long);
+  const size_t off_tf3 = (off_dcnt + (size_t)W * 3 * k * sizeof(int32_t) + 255) / 256 * 256;
+  const size_t work_bytes = off_tf3 + (size_t)W * 3 * mc * sizeof(double);
+  const size_t map_bytes = (size_t)bm::kMaxXcd * (W + 1) * sizeof(int32_t);
+  const size_t rres_bytes = 16 + (size_t)W * sizeof(double) + (size_t)W * p.passes_p * sizeof(bm::PassOut);
+  if (c->rwork.bytes < work_bytes || c->wgmap.bytes < map_bytes || c->rres.bytes < rres_bytes) {
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (c->rwork.bytes < work_bytes) BM_TRY(dev_alloc(c, c->rwork, work_bytes));
+    if (c->wgmap.bytes < map_bytes) BM_TRY(dev_alloc(c, c->wgmap, map_bytes));
+    if (c->rres.bytes < rres_bytes) BM_TRY(dev_alloc(c, c->rres, rres_bytes));
+  }
+  int32_t* d_map = P<int32_t>(c->wgmap);
+  BM_TRY(upload(c, d_map, xnw.data(), bm::kMaxXcd * sizeof(int32_t)));
+  BM_TRY(upload(c, d_map + bm::kMaxXcd, xw.data(), (size_t)bm::kMaxXcd * W * sizeof(int32_t)));
+  BM_TRY(upload(c, P<int64_t>(c->sizes), sizes.data(), W * sizeof(int64_t)));
+  BM_TRY(upload(c, P<int32_t>(c->rflags), recalc.data(), W * sizeof(int32_t)));
+  unsigned char* rr = P<unsigned char>(c->rres);
+  unsigned char* wk = P<unsigned char>(c->rwork);
+  HIP_TRY(c, hipMemsetAsync(rr, 0, 16, c->stream));
+  HIP_TRY(c, hipMemsetAsync(wk, 0, off_tf3, c->stream));
+
+  const int64_t Sj = c->max_s * cp;
+  bm::RoundArgs r{};
+  r.X = X;
+  r.m = p.m;
+  r.n = n;
+  r.cp = cp;
+  r.k = k;
+  r.W = W;
+  r.passes_p = p.passes_p;
+  r.max_iter = p.max_iter;
+  r.n_cand = p.n_candidates;
+  r.t = t;
+  r.seed = p.seed;
+  r.tol = p.tol;
+  r.s = P<int64_t>(c->sizes);
+  r.recalc = P<int32_t>(c->rflags);
+  r.xcd_nw = d_map;
+  r.xcd_workers = d_map + bm::kMaxXcd;
+  r.reg = reinterpret_cast<unsigned int*>(wk);
+  r.gbar = reinterpret_cast<bm::GroupBar*>(wk + off_gbar);
+  r.bar = reinterpret_cast<bm::GroupBar*>(wk + off_bar);
+  r.delta = reinterpret_cast<unsigned long long*>(wk + off_delta);
+  r.dcnt = reinterpret_cast<int32_t*>(wk + off_dcnt);
+  r.tf3 = reinterpret_cast<double*>(wk + off_tf3);
+  bm::AssignArgs& a = r.as;
+  a.S = P<float>(c->S);
+  a.S_stride = Sj;
+  a.ld = cp;
+  a.n = n;
+  a.cp = cp;
+  a.k = k;
+  a.tile_pts = 0;
+  a.max_chunks = (int32_t)mc;
+  a.vec = 1;
+  a.s = r.s;
+  a.Cp = P<float>(c->Cp);
+  a.C_stride = (int64_t)k * cp;
+  a.cn = P<float>(c->cn);
+  a.cn_stride = k;
+  a.labels = P<int32_t>(c->labels);
+  a.lab_stride = c->max_s;
+  a.tf = P<double>(c->tf);
+  a.tnear = nullptr;
+  a.acc = P<unsigned long long>(c->acc);
+  a.cnt = P<int32_t>(c->cnt);
+  a.scale = P<double>(c->scale);
+  a.st = nullptr;
+  bm::KppArgs& ka = r.ka;
+  ka.S = a.S;
+  ka.S_stride = Sj;
+  ka.ld = cp;
+  ka.n = n;
+  ka.cp = cp;
+  ka.k = k;
+  ka.ndt_max = (int32_t)mc;
+  ka.njobs = c->max_jobs;
+  ka.s = r.s;
+  ka.Cp = P<float>(c->Cp);
+  ka.C_stride = (int64_t)k * cp;
+  ka.deg = P<uint8_t>(c->deg_work);
+  ka.D = P<float>(c->D);
+  ka.D_slot_stride = (int64_t)c->max_jobs * c->max_s;
+  ka.D_job_stride = c->max_s;
+  ka.Dt = P<double>(c->Dt);
+  ka.ks = P<KppState>(c->ks);
+  ka.todo = P<int32_t>(c->todo);
+  ka.picks = nullptr;
+  ka.seed_worker = P<uint64_t>(c->seed_worker);
+  ka.g = 0;
+  ka.gs = P<uint64_t>(c->gs);
+  ka.n_cand = p.n_candidates;
+  r.inv_scale = P<double>(c->inv_scale);
+  r.Cinc = P<float>(c->Cinc);
+  r.deg_inc = P<uint8_t>(c->deg_inc);
+  r.fhat = P<double>(c->fhat);
+  r.Cp = P<float>(c->Cp);
+  r.deg_work = P<uint8_t>(c->deg_work);
+  r.err = reinterpret_cast<int32_t*>(rr);
+  r.recalc_f = reinterpret_cast<double*>(rr + 16);
+  r.out = reinterpret_cast<bm::PassOut*>(rr + 16 + (size_t)W * sizeof(double));
+  BM_TRY(upload(c, c->rargs.p, &r, sizeof r));
+
+  HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
+  HIP_TRY(c, bm::launch_round(c->stream, P<bm::RoundArgs>(c->rargs), cp, cap, lds));
+  HIP_TRY(c, hipEventRecord(c->ev2, c->stream));
+  std::vector<unsigned char> h(rres_bytes);
+  BM_TRY(readback(c, rr, rres_bytes, h.data()));
+  float ms = 0.f;
+  HIP_TRY(c, hipEventElapsedTime(&ms, c->ev1, c->ev2));
+  res->seconds = ms * 1e-3;
+  int32_t err;
+  std::memcpy(&err, h.data(), sizeof err);
+  if (err == 2) return kRoundNoFit;
+  if (err) return c->fail(BM_E_STATE, "persistent round kernel: a group barrier timed out");
+  res->recalc_f.assign(W, 0.0);
+  std::memcpy(res->recalc_f.data(), h.data() + 16, W * sizeof(double));
+  res->out.resize((size_t)W * p.passes_p);
+  std::memcpy(res->out.data(), h.data() + 16 + W * sizeof(double),
+              (size_t)W * p.passes_p * sizeof(bm::PassOut));
+  return BM_OK;
+}
+
 int check_prec(bm_ctx* c, int prec) {
   if (prec != BM_FP32) return c->fail(BM_E_ARG, "precision %d is not available (BM_FP32 only)", prec);
   return BM_OK;
@@ -660,7 +863,8 @@ BM_API void bm_destroy(bm_ctx* c) {
                     &c->sizes,    &c->tile_job,  &c->tile_idx,
                     &c->rkeys,    &c->seed_worker, &c->absmax, &c->scale,   &c->inv_scale,
                     &c->fjob,     &c->nearjob, &c->D,         &c->Dt,
-                    &c->ks,       &c->todo,    &c->picks};
+                    &c->ks,       &c->todo,    &c->picks,    &c->gs,        &c->rflags,
+                    &c->wgmap,    &c->rargs,   &c->rres,     &c->bars, &c->rwork};
   for (DevBuf* b : bufs) dev_free(*b);
   for (int i = 0; i < kNumStage; ++i) {
     if (c->stage[i]) (void)hipHostFree(c->stage[i]);
@@ -878,15 +1082,56 @@ BM_API int bm_bigmeans_run(bm_ctx* c, const float* X, const bm_params* params, f
 
   // The batch a pass runs on: all workers together, or one worker alone.
   std::vector<std::pair<int, int>> groups;
-  if (p.batched)
+  if (p.batched != 0)
     groups.push_back({0, W});
   else
     for (int w = 0; w < W; ++w) groups.push_back({w, 1});
+
+  if (p.batched == 1) BM_TRY(upload(c, c->seed_worker.p, sw.data(), 2 * W * sizeof(uint64_t)));
 
   for (int t = 0; t < p.rounds_T; ++t) {
     int64_t rpass[kNBins] = {0}, racc[kNBins] = {0};
     for (int w = 0; w < W; ++w) s_new[w] = draw_size(p, (uint32_t)w, t, bacc, bpass, &bin_cur[w]);
 
+    // persistent round: re-evaluations and all passes of all workers in one
+    // launch (the multi-launch path below runs when it does not fit the device)
+    bool round_done = false;
+    std::vector<int32_t> rflag(W, 0);
+    RoundResult rres;
+    if (p.batched == 1 && c->round_ok) {
+      for (int w = 0; w < W; ++w) rflag[w] = (std::isfinite(fhat[w]) && s_new[w] != s_cur[w]) ? 1 : 0;
+      const int rc = round_persistent(c, X, p, t, s_new, rflag, &rres);
+      if (rc == kRoundNoFit) c->round_ok = false;
+      else BM_TRY(rc);
+      round_done = rc == BM_OK;
+    }
+    if (round_done) {
+      lloyd_ms += rres.seconds * 1e3;
+      int64_t round_dists = 0;
+      for (int w = 0; w < W; ++w) {
+        s_cur[w] = s_new[w];
+        if (rflag[w]) fhat[w] = rres.recalc_f[w];
+        for (int q = 0; q < p.passes_p; ++q) {
+          const bm::PassOut& o = rres.out[(size_t)w * p.passes_p + q];
+          lloyd_iters += o.iters + 1;
+          round_dists += (int64_t)(o.iters + 1) * s_cur[w] * k;
+          rpass[bin_cur[w]] += 1;
+          if (o.accepted) {
+            fhat[w] = o.f;
+            ndeg[w] = o.ndeg;
+            Lsum += s_cur[w];
+            Lcount += 1;
+            racc[bin_cur[w]] += 1;
+          }
+        }
+      }
+      lloyd_dists += round_dists;
+      if (c->prof) {
+        c->stats.assign_launches += 1;
+        c->stats.assign_seconds += rres.seconds;
+        c->stats.assign_dists += round_dists;
+      }
+    } else {  // multi-launch passes
     // Re-evaluate incumbents whose sample size changed (Algorithm 1; Section 4.2).
     std::vector<int> rec;
     for (int w = 0; w < W; ++w)
@@ -987,6 +1232,7 @@ BM_API int bm_bigmeans_run(bm_ctx* c, const float* X, const bm_params* params, f
         }
       }
     }
+    }  // multi-launch passes
     for (int i = 0; i < kNBins; ++i) {
       bacc[i] += racc[i];
       bpass[i] += rpass[i];

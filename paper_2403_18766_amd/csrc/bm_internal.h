@@ -131,9 +131,66 @@ struct KppArgs {
   int32_t* todo;         // [job][k]
   int32_t* picks;        // [job][k][4] or nullptr
   const uint64_t* seed_worker;  // [job][2]: seed, worker
-  uint64_t g;
+  uint64_t g;            // global pass index of the draws (when gs is null)
+  const uint64_t* gs;    // [job] global pass index per job (persistent rounds), or null
   int32_t n_cand;
 };
+// Persistent round kernel: every worker runs its (optional) re-evaluation
+// and passes_p passes of Algorithm 1 on its own group of workgroups.
+struct PassOut {
+  int32_t accepted;  // the pass replaced the incumbent
+  int32_t iters;     // centroid updates of its Lloyd run
+  int32_t ndeg;      // empty clusters of the Lloyd result
+  int32_t pad_;
+  double f;          // objective of the Lloyd result on the pass's sample
+};
+
+struct GroupBar {
+  unsigned int count;
+  unsigned int gen;
+  unsigned int pad_[14];  // one 64-byte line per worker
+};
+
+constexpr int kMaxXcd = 16;  // XCD ids are taken modulo this
+
+struct RoundArgs {
+  const float* X;
+  int64_t m;
+  int32_t n, cp, k, W, passes_p, max_iter, n_cand, t;
+  uint64_t seed;
+  double tol;
+  const int64_t* s;            // [W] sample size of each worker this round
+  const int32_t* recalc;       // [W] re-evaluate the incumbent on a fresh sample first
+  const int32_t* xcd_nw;       // [kMaxXcd] number of workers placed on each XCD
+  const int32_t* xcd_workers;  // [kMaxXcd][W] the workers placed on each XCD
+  unsigned int* reg;           // [kMaxXcd] registration counters (zero at launch)
+  GroupBar* gbar;              // device-wide barrier (zero at launch)
+  GroupBar* bar;               // [W] worker barriers (zero at launch)
+  AssignArgs as;               // job = worker (S, labels, scale, layout)
+  KppArgs ka;                  // job = worker
+  unsigned long long* delta;   // [W][3][k*cp] fixed-point sum deltas (zero at launch)
+  int32_t* dcnt;               // [W][3][k] count deltas (zero at launch)
+  double* tf3;                 // [W][3][max_chunks] chunk objective partials
+  const double* inv_scale;     // [cp]
+  float* Cinc;                 // [W][k][n] incumbents
+  uint8_t* deg_inc;            // [W][k]
+  double* fhat;                // [W]
+  float* Cp;                   // [W][k][cp] working copy for K-means++
+  uint8_t* deg_work;           // [W][k]
+  PassOut* out;                // [W][passes_p]
+  double* recalc_f;            // [W]
+  int32_t* err;                // 1: a barrier timed out; 2: an XCD holds fewer workgroups than workers
+};
+
+// XCD id of every workgroup of a grid-sized launch: out[grid].
+hipError_t launch_xcd_probe(hipStream_t st, uint32_t* out, int32_t grid);
+// Largest grid of k_round<cp> that is co-resident on the device.
+hipError_t round_capacity(int32_t cp, size_t lds, int* blocks);
+size_t round_lds_bytes(int32_t cp, int32_t k);
+// r_dev: the RoundArgs in device memory (read by every workgroup).
+hipError_t launch_round(hipStream_t st, const RoundArgs* r_dev, int32_t cp, int32_t grid,
+                        size_t lds);
+
 hipError_t launch_kpp_setup(hipStream_t st, const KppArgs& a, int32_t njobs);
 hipError_t launch_kpp_init(hipStream_t st, const KppArgs& a, int32_t njobs, int64_t max_s);
 hipError_t launch_kpp_step(hipStream_t st, const KppArgs& a, int32_t njobs);

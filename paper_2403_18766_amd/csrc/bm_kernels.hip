@@ -135,46 +135,59 @@ __device__ inline float dist_direct_reg(const float (&x)[NP], const float* __res
 // thread.  Phase 2: the workgroup copies its 256 rows with consecutive
 // threads on consecutive 16-byte pieces of a row.
 // ---------------------------------------------------------------------------
-template <bool VEC>
+// One block of up to 256 sample elements starting at `base`: Feistel index
+// per thread, then the workgroup copies the rows (consecutive threads on
+// consecutive 16-byte pieces of a row when vec).  Sj points at row 0 of the
+// job's sample; idxj (nullable) at its index 0.
+__device__ inline void sample_block(const float* __restrict__ X, int n, const FeistelKey& fk,
+                                    int64_t sj, int64_t base, int32_t* __restrict__ idxj,
+                                    float* __restrict__ Sj, int ld, bool vec) {
+  __shared__ int64_t rows[kWG];
+  const int64_t i = base + threadIdx.x;
+  if (i < sj) {
+    const uint64_t y = feistel_index((uint64_t)i, fk);
+    rows[threadIdx.x] = (int64_t)y;
+    if (idxj) idxj[i] = (int32_t)y;
+  }
+  __syncthreads();
+  if (Sj != nullptr) {
+    const int nrows = (int)min((int64_t)kWG, sj - base);
+    float* __restrict__ Sb = Sj + base * ld;
+    if (vec) {
+      const int nv = n >> 2, lv = ld >> 2;
+      for (int e = threadIdx.x; e < nrows * lv; e += kWG) {
+        const int r = e / lv, c = e - r * lv;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (c < nv) v = reinterpret_cast<const float4*>(X + rows[r] * (int64_t)n)[c];
+        reinterpret_cast<float4*>(Sb + (int64_t)r * ld)[c] = v;
+      }
+    } else {
+      for (int e = threadIdx.x; e < nrows * ld; e += kWG) {
+        const int r = e / ld, c = e - r * ld;
+        Sb[(int64_t)r * ld + c] = c < n ? X[rows[r] * (int64_t)n + c] : 0.f;
+      }
+    }
+  }
+  __syncthreads();  // rows[] is reused by the next block
+}
+
 __global__ __launch_bounds__(kWG) void k_sample(const float* __restrict__ X, int64_t m, int n,
                                                  const int64_t* __restrict__ sizes,
                                                  const uint64_t* __restrict__ rkeys,
                                                  int32_t* __restrict__ idx, int64_t idx_stride,
-                                                 float* __restrict__ S, int64_t S_stride, int ld) {
+                                                 float* __restrict__ S, int64_t S_stride, int ld,
+                                                 int vec) {
   const int job = blockIdx.y;
   const int64_t sj = sizes[job];
   const int64_t base = (int64_t)blockIdx.x * kWG;
   if (base >= sj) return;
-  __shared__ int64_t rows[kWG];
   FeistelKey fk;
 #pragma unroll
   for (int r = 0; r < 4; ++r) fk.rk[r] = rkeys[job * 4 + r];
   fk.m = (uint64_t)m;
   fk.h = feistel_half_bits((uint64_t)m);
-  const int64_t i = base + threadIdx.x;
-  if (i < sj) {
-    const uint64_t y = feistel_index((uint64_t)i, fk);
-    rows[threadIdx.x] = (int64_t)y;
-    if (idx) idx[job * idx_stride + i] = (int32_t)y;
-  }
-  __syncthreads();
-  if (S == nullptr) return;
-  const int nrows = (int)min((int64_t)kWG, sj - base);
-  float* __restrict__ Sj = S + job * S_stride + base * ld;
-  if (VEC) {
-    const int nv = n >> 2, lv = ld >> 2;
-    for (int e = threadIdx.x; e < nrows * lv; e += kWG) {
-      const int r = e / lv, c = e - r * lv;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (c < nv) v = reinterpret_cast<const float4*>(X + rows[r] * (int64_t)n)[c];
-      reinterpret_cast<float4*>(Sj + (int64_t)r * ld)[c] = v;
-    }
-  } else {
-    for (int e = threadIdx.x; e < nrows * ld; e += kWG) {
-      const int r = e / ld, c = e - r * ld;
-      Sj[(int64_t)r * ld + c] = c < n ? X[rows[r] * (int64_t)n + c] : 0.f;
-    }
-  }
+  sample_block(X, n, fk, sj, base, idx ? idx + job * idx_stride : nullptr,
+               S ? S + job * S_stride : nullptr, ld, vec != 0);
 }
 
 // Per-dimension max |x| as float bits (non-negative floats order like uints).
@@ -287,18 +300,15 @@ __device__ inline long long quantize(float x, double scale) {
 // every wave waiting on a chain of cache misses); the distance loop then
 // reads each centroid row as LDS broadcasts and feeds it to PPL*NP FMAs.
 template <int NP, int PPL, bool SUMS>
-__global__ __launch_bounds__(kWG) void k_assign_small(AssignArgs a) {
-  const int job = a.tile_job[blockIdx.x];
-  const int t = a.tile_idx[blockIdx.x];
-  int first_assign = 0;
-  if (a.st) {
-    const JobState st = a.st[job];
-    if (!st.active) return;
-    first_assign = st.iter == 0;
+__device__ inline void assign_range(const AssignArgs& a, int job, int64_t p_begin, int64_t p_end,
+                                    int first_assign, unsigned char* smem, bool staged = false,
+                                    double* tfj = nullptr, unsigned long long* accj = nullptr,
+                                    int32_t* cntj = nullptr) {
+  if (tfj == nullptr) tfj = a.tf + (int64_t)job * a.max_chunks;
+  if (SUMS && accj == nullptr) {
+    accj = a.acc + (int64_t)job * a.k * NP;
+    cntj = a.cnt + (int64_t)job * a.k;
   }
-  const int64_t s = a.s[job];
-  const int64_t p_begin = (int64_t)t * a.tile_pts;
-  const int64_t p_end = min(s, p_begin + a.tile_pts);
   const float* __restrict__ S = a.S + job * a.S_stride;
   const float* __restrict__ Cg = a.Cp + job * a.C_stride;
   const float* __restrict__ cng = a.cn + job * a.cn_stride;
@@ -309,34 +319,44 @@ __global__ __launch_bounds__(kWG) void k_assign_small(AssignArgs a) {
   const int ld = a.ld;
 
   // LDS: [k][NP] centroids, [k] norms, then (SUMS) [k][NP] int64 sums, [k] counts
-  extern __shared__ __align__(16) unsigned char smem[];
   float* sC = reinterpret_cast<float*>(smem);
   float* sCn = sC + k * NP;
   unsigned long long* lds_acc =
       reinterpret_cast<unsigned long long*>(smem + (((size_t)k * NP + k) * 4 + 15) / 16 * 16);
   int* lds_cnt = reinterpret_cast<int*>(lds_acc + k * NP);
-  __shared__ double red_f[4];
-  __shared__ int red_i[4];
+  // per-wave chunk partials, double-buffered over loop iterations
+  __shared__ double red_f[2][PPL][4];
+  __shared__ int red_i[2][PPL][4];
 
-  for (int e = threadIdx.x; e < k * NP / 4; e += kWG)
-    reinterpret_cast<float4*>(sC)[e] = reinterpret_cast<const float4*>(Cg)[e];
-  for (int e = threadIdx.x; e < k; e += kWG) sCn[e] = cng[e];
-  if (SUMS) {
-    for (int e = threadIdx.x; e < k * NP; e += kWG) lds_acc[e] = 0ull;
-    for (int e = threadIdx.x; e < k; e += kWG) lds_cnt[e] = 0;
+  if (!staged) {
+    // centroids not yet in LDS: one coalesced copy; LDS sums start at zero
+    for (int e = threadIdx.x; e < k * NP / 4; e += kWG)
+      reinterpret_cast<float4*>(sC)[e] = reinterpret_cast<const float4*>(Cg)[e];
+    for (int e = threadIdx.x; e < k; e += kWG) sCn[e] = cng[e];
+    if (SUMS) {
+      for (int e = threadIdx.x; e < k * NP; e += kWG) lds_acc[e] = 0ull;
+      for (int e = threadIdx.x; e < k; e += kWG) lds_cnt[e] = 0;
+    }
+    __syncthreads();
   }
-  __syncthreads();
+  // staged: the caller has placed centroids and norms in LDS, synchronised,
+  // and keeps the LDS sums at zero between calls (the flush below clears them)
 
-  float cmax2 = 0.f;
-  for (int j = 0; j < k; ++j) cmax2 = fmaxf(cmax2, sCn[j]);
+  float cmax2 = 0.f;  // max_j ||c_j||^2 (max is exact in any order)
+  for (int j = threadIdx.x & 63; j < k; j += 64) cmax2 = fmaxf(cmax2, sCn[j]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) cmax2 = fmaxf(cmax2, __shfl_xor(cmax2, off, 64));
   const float cmax = sqrtf(cmax2) * 1.0000002f;
   // two interleaved FMA chains of NP/2 terms per dot product, then one add
   constexpr float kTerms = (float)(NP / 2 + 1);
   const float gam = kTerms * kU / (1.f - kTerms * kU);
   const float kB = 2.f * (2.f * gam + 2.f * kU);
   const bool vec = a.vec != 0;
+  const bool want_near = a.tnear != nullptr;
+  const int wv = threadIdx.x >> 6;
 
   int changed = 0;
+  int par = 0;
   for (int64_t base = p_begin; base < p_end; base += kWG * PPL) {
     float x[PPL][NP];
     bool valid[PPL];
@@ -446,33 +466,72 @@ __global__ __launch_bounds__(kWG) void k_assign_small(AssignArgs a) {
           if (jo >= 0) atomicAdd(&lds_cnt[jo], -1);
         }
       }
-      // objective and near-tie count of this 256-point chunk
-      const double ft = block_sum_f64(fpart, red_f);
-      const int nt = block_sum_i32(near, red_i);
-      const int64_t cbase = base + kWG * p;
-      if (threadIdx.x == 0 && cbase < p_end) {
-        const int64_t ch = (int64_t)job * a.max_chunks + cbase / kWG;
-        a.tf[ch] = ft;
-        if (a.tnear) a.tnear[ch] = nt;
+      // wave partials of this 256-point chunk's objective and near-tie count
+      fpart = wave_sum_f64(fpart);
+      if ((threadIdx.x & 63) == 0) red_f[par][p][wv] = fpart;
+      if (want_near) {
+        near = wave_sum_i32(near);
+        if ((threadIdx.x & 63) == 0) red_i[par][p][wv] = near;
       }
     }
+    // one synchronisation for all chunks of this iteration; the buffers of
+    // the other parity are rewritten only after the next one
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int p = 0; p < PPL; ++p) {
+        const int64_t cbase = base + kWG * p;
+        if (cbase < p_end) {
+          const double* r4 = red_f[par][p];
+          tfj[cbase / kWG] = (r4[0] + r4[1]) + (r4[2] + r4[3]);
+          if (want_near) {
+            const int* q4 = red_i[par][p];
+            a.tnear[(int64_t)job * a.max_chunks + cbase / kWG] = (q4[0] + q4[1]) + (q4[2] + q4[3]);
+          }
+        }
+      }
+    }
+    par ^= 1;
   }
 
   if (SUMS) {
     const int any = __syncthreads_or(changed);
     if (any) {
-      unsigned long long* dst = a.acc + (int64_t)job * k * NP;
       for (int e = threadIdx.x; e < k * NP; e += kWG) {
         const unsigned long long v = lds_acc[e];
-        if (v) atomicAdd(&dst[e], v);
+        if (v) {
+          atomicAdd(&accj[e], v);
+          if (staged) lds_acc[e] = 0ull;
+        }
       }
-      int32_t* cdst = a.cnt + (int64_t)job * k;
       for (int e = threadIdx.x; e < k; e += kWG) {
         const int v = lds_cnt[e];
-        if (v) atomicAdd(&cdst[e], v);
+        if (v) {
+          atomicAdd(&cntj[e], v);
+          if (staged) lds_cnt[e] = 0;
+        }
       }
     }
   }
+  __syncthreads();  // the LDS is reused by whatever the workgroup does next
+}
+
+// Multi-launch form: one workgroup per tile of the flattened tile map.
+template <int NP, int PPL, bool SUMS>
+__global__ __launch_bounds__(kWG) void k_assign_small(AssignArgs a) {
+  const int job = a.tile_job[blockIdx.x];
+  const int t = a.tile_idx[blockIdx.x];
+  int first_assign = 0;
+  if (a.st) {
+    const JobState st = a.st[job];
+    if (!st.active) return;
+    first_assign = st.iter == 0;
+  }
+  const int64_t s = a.s[job];
+  const int64_t p_begin = (int64_t)t * a.tile_pts;
+  const int64_t p_end = min(s, p_begin + a.tile_pts);
+  extern __shared__ __align__(16) unsigned char smem[];
+  assign_range<NP, PPL, SUMS>(a, job, p_begin, p_end, first_assign, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -480,8 +539,7 @@ __global__ __launch_bounds__(kWG) void k_assign_small(AssignArgs a) {
 // partials; stop (f_prev - f <= tol f, f not finite, or max_iter updates) or
 // move every non-empty centroid to fp32(sum / count) and recompute its norm.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kWG) void k_finalize(FinalizeArgs a) {
-  const int job = blockIdx.x;
+__device__ __noinline__ void finalize_job(const FinalizeArgs& a, int job, double* sh_sq /* [k][cp] LDS */) {
   JobState st = a.st[job];
   if (!st.active) return;
   const int k = a.k, cp = a.cp;
@@ -489,7 +547,6 @@ __global__ __launch_bounds__(kWG) void k_finalize(FinalizeArgs a) {
   __shared__ int sh_upd;
   __shared__ int sh_acc;
   __shared__ int sh_empty;
-  extern __shared__ double sh_sq[];  // [k][cp]
   if (threadIdx.x < 64) {
     const double f = wave_chunked_sum(a.tf + (int64_t)job * a.max_chunks, st.nchunks);
     const bool stop = (st.iter > 0 && st.f_prev - f <= a.tol * f) || !isfinite(f) ||
@@ -558,15 +615,19 @@ __global__ __launch_bounds__(kWG) void k_finalize(FinalizeArgs a) {
     }
     a.st[job] = st;
   }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kWG) void k_finalize(FinalizeArgs a) {
+  extern __shared__ double sh_sq[];
+  finalize_job(a, blockIdx.x, sh_sq);
 }
 
 // Start of a Lloyd run: job state, zero cluster sums and counts, and the
 // norms ||c_j||^2 (FP64, rounded once) of the starting centroids.
-__global__ __launch_bounds__(kWG) void k_job_init(JobState* js, const int64_t* sizes, int k, int cp,
-                                                  unsigned long long* acc, int32_t* cnt,
-                                                  const float* __restrict__ Cp,
-                                                  float* __restrict__ cn) {
-  const int j = blockIdx.x;
+__device__ __noinline__ void job_init_one(JobState* js, const int64_t* sizes, int k, int cp,
+                             unsigned long long* acc, int32_t* cnt, const float* __restrict__ Cp,
+                             float* __restrict__ cn, int j) {
   for (int e = threadIdx.x; e < k * cp; e += kWG) acc[(int64_t)j * k * cp + e] = 0ull;
   for (int e = threadIdx.x; e < k; e += kWG) cnt[(int64_t)j * k + e] = 0;
   for (int r = threadIdx.x; r < k; r += kWG) {
@@ -587,6 +648,14 @@ __global__ __launch_bounds__(kWG) void k_job_init(JobState* js, const int64_t* s
     st.pad_ = 0;
     js[j] = st;
   }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kWG) void k_job_init(JobState* js, const int64_t* sizes, int k, int cp,
+                                                  unsigned long long* acc, int32_t* cnt,
+                                                  const float* __restrict__ Cp,
+                                                  float* __restrict__ cn) {
+  job_init_one(js, sizes, k, cp, acc, cnt, Cp, cn, blockIdx.x);
 }
 
 // Objective of each job: fixed-order sum of its chunk partials (one wave per job).
@@ -611,17 +680,23 @@ __global__ __launch_bounds__(64) void k_reduce_f(const double* __restrict__ tf,
 }
 
 // Start of a pass: working centroids and degenerate flags from the incumbent.
-__global__ __launch_bounds__(kWG) void k_copy_incumbent(const float* __restrict__ Cinc,
-                                                         const uint8_t* __restrict__ deg_inc,
-                                                         int n, int cp, int k,
-                                                         float* __restrict__ Cp,
-                                                         uint8_t* __restrict__ deg_work) {
-  const int job = blockIdx.x;
+__device__ __noinline__ void copy_incumbent_one(const float* __restrict__ Cinc,
+                                   const uint8_t* __restrict__ deg_inc, int n, int cp, int k,
+                                   float* __restrict__ Cp, uint8_t* __restrict__ deg_work,
+                                   int job) {
   for (int e = threadIdx.x; e < k * cp; e += kWG) {
     const int r = e / cp, d = e - r * cp;
     Cp[(int64_t)job * k * cp + e] = d < n ? Cinc[((int64_t)job * k + r) * n + d] : 0.f;
   }
   for (int e = threadIdx.x; e < k; e += kWG) deg_work[(int64_t)job * k + e] = deg_inc[(int64_t)job * k + e];
+}
+
+__global__ __launch_bounds__(kWG) void k_copy_incumbent(const float* __restrict__ Cinc,
+                                                         const uint8_t* __restrict__ deg_inc,
+                                                         int n, int cp, int k,
+                                                         float* __restrict__ Cp,
+                                                         uint8_t* __restrict__ deg_work) {
+  copy_incumbent_one(Cinc, deg_inc, n, cp, k, Cp, deg_work, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -631,8 +706,19 @@ __global__ __launch_bounds__(kWG) void k_copy_incumbent(const float* __restrict_
 // ---------------------------------------------------------------------------
 __device__ inline int other_slot(int dcur, int c) { return c < dcur ? c : c + 1; }
 
-__global__ __launch_bounds__(kWG) void k_kpp_setup(KppArgs a) {
-  const int job = blockIdx.x;
+// A job's K-means++ state, read through the vector memory path (it may have
+// been written by another workgroup before the last barrier).
+__device__ inline KppState load_ks(const KppState* p) {
+  KppState ks;
+  const volatile unsigned long long* pd = reinterpret_cast<const volatile unsigned long long*>(p);
+  unsigned long long* qd = reinterpret_cast<unsigned long long*>(&ks);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(KppState) / 8); ++i) qd[i] = pd[i];
+  return ks;
+}
+
+
+__device__ __noinline__ void kpp_setup_job(const KppArgs& a, int job) {
   const int k = a.k;
   if (a.picks) {
     for (int e = threadIdx.x; e < 4 * k; e += kWG) a.picks[(int64_t)job * 4 * k + e] = -1;
@@ -653,16 +739,18 @@ __global__ __launch_bounds__(kWG) void k_kpp_setup(KppArgs a) {
     ks.uniform = 0;
     a.ks[job] = ks;
   }
+  __syncthreads();
 }
 
-// D_i = min over kept centroids of ||S_i - c_j||^2 (slot 0) and tile sums.
-__global__ __launch_bounds__(kWG) void k_kpp_init(KppArgs a) {
-  const int job = blockIdx.y;
-  const KppState ks = a.ks[job];
+__global__ __launch_bounds__(kWG) void k_kpp_setup(KppArgs a) { kpp_setup_job(a, blockIdx.x); }
+
+// D_i = min over kept centroids of ||S_i - c_j||^2 (slot 0) and the tile's sum.
+__device__ __noinline__ void kpp_init_tile(const KppArgs& a, int job, int64_t tile) {
+  const KppState ks = load_ks(a.ks + job);
   if (ks.ntodo == 0 || !ks.has_d) return;
   const int64_t s = a.s[job];
-  const int64_t i = (int64_t)blockIdx.x * kDTile + threadIdx.x;
-  if ((int64_t)blockIdx.x * kDTile >= s) return;
+  const int64_t i = tile * kDTile + threadIdx.x;
+  if (tile * kDTile >= s) return;
   const float* S = a.S + job * a.S_stride;
   const float* C = a.Cp + job * a.C_stride;
   const uint8_t* deg = a.deg + (int64_t)job * a.k;
@@ -674,7 +762,11 @@ __global__ __launch_bounds__(kWG) void k_kpp_init(KppArgs a) {
   }
   __shared__ double red[4];
   const double ts = block_sum_f64(i < s ? (double)dmin : 0.0, red);
-  if (threadIdx.x == 0) a.Dt[(0 * (int64_t)a.njobs + job) * a.ndt_max + blockIdx.x] = ts;
+  if (threadIdx.x == 0) a.Dt[(0 * (int64_t)a.njobs + job) * a.ndt_max + tile] = ts;
+}
+
+__global__ __launch_bounds__(kWG) void k_kpp_init(KppArgs a) {
+  kpp_init_tile(a, blockIdx.y, blockIdx.x);
 }
 
 // Wave-level monotone prefix over v[0..cnt): lane l sums a contiguous chunk
@@ -726,10 +818,9 @@ __device__ inline double wave_prefix_search(const T* v, int64_t cnt, double tau,
   return total;
 }
 
-// One workgroup per job: commit the pending step, then draw the next one.
-// Only wave 0 works (scans and searches are wave-level).
-__global__ __launch_bounds__(64) void k_kpp_step(KppArgs a) {
-  const int job = blockIdx.x;
+// One wave per job: commit the pending step, then draw the next one (scans
+// and searches are wave-level; lane = threadIdx.x, which must be < 64).
+__device__ __noinline__ void kpp_step_job(const KppArgs& a, int job) {
   KppState ks = a.ks[job];
   const int64_t s = a.s[job];
   const int k = a.k;
@@ -765,7 +856,8 @@ __global__ __launch_bounds__(64) void k_kpp_step(KppArgs a) {
   if (ks.step < ks.ntodo) {
     uint64_t k0, k1;
     stream_key(a.seed_worker[job * 2], (uint32_t)a.seed_worker[job * 2 + 1], 3u, &k0, &k1);
-    const U64x4 w = philox_ctr((uint64_t)ks.step, a.g, 0, 0, k0, k1);
+    const uint64_t g = a.gs ? a.gs[job] : a.g;
+    const U64x4 w = philox_ctr((uint64_t)ks.step, g, 0, 0, k0, k1);
     const double* dt = a.Dt + ((int64_t)ks.dcur * a.njobs + job) * a.ndt_max;
     if (ks.has_d && ks.step == 0) ks.T = wave_prefix_search<double>(dt, ndt, -1.0, nullptr, nullptr);
     if (!ks.has_d || !(ks.T > 0.0 && ks.T < __builtin_inf())) {
@@ -807,15 +899,16 @@ __global__ __launch_bounds__(64) void k_kpp_step(KppArgs a) {
   if (lane == 0) a.ks[job] = ks;
 }
 
+__global__ __launch_bounds__(64) void k_kpp_step(KppArgs a) { kpp_step_job(a, blockIdx.x); }
+
 // Potentials of the pending candidates: new D per candidate into the other
 // slots, with per-tile sums.
-__global__ __launch_bounds__(kWG) void k_kpp_pot(KppArgs a) {
-  const int job = blockIdx.y;
-  const KppState ks = a.ks[job];
+__device__ __noinline__ void kpp_pot_tile(const KppArgs& a, int job, int64_t tile) {
+  const KppState ks = load_ks(a.ks + job);
   if (ks.ncand == 0) return;
   const int64_t s = a.s[job];
-  if ((int64_t)blockIdx.x * kDTile >= s) return;
-  const int64_t i = (int64_t)blockIdx.x * kDTile + threadIdx.x;
+  if (tile * kDTile >= s) return;
+  const int64_t i = tile * kDTile + threadIdx.x;
   const float* S = a.S + job * a.S_stride;
   __shared__ double red[4];
   float dcur = 0.f;
@@ -830,8 +923,402 @@ __global__ __launch_bounds__(kWG) void k_kpp_pot(KppArgs a) {
     }
     const double ts = block_sum_f64(i < s ? (double)m : 0.0, red);
     if (threadIdx.x == 0)
-      a.Dt[((int64_t)other_slot(ks.dcur, c) * a.njobs + job) * a.ndt_max + blockIdx.x] = ts;
+      a.Dt[((int64_t)other_slot(ks.dcur, c) * a.njobs + job) * a.ndt_max + tile] = ts;
   }
+}
+
+__global__ __launch_bounds__(kWG) void k_kpp_pot(KppArgs a) {
+  kpp_pot_tile(a, blockIdx.y, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent round kernel (cooperative launch: all workgroups co-resident).
+//
+// Each workgroup reads the id of the XCD it runs on and registers there; after
+// one device-wide barrier every workgroup knows how many workgroups each XCD
+// holds, and splits its XCD's workgroups among the workers the host placed on
+// that XCD (in proportion to their sample sizes, at least one each).  A worker
+// therefore lives inside one XCD: its workgroups share that XCD's L2, so its
+// group barrier needs no L2 write-back or invalidation — only completed
+// stores, L2 atomics and an L1 invalidation.  Buffers updated by atomics
+// (fixed-point deltas, counts, barrier words) are only ever accessed through
+// atomics.  Workers never wait for each other.
+//
+// Lloyd needs one barrier per iteration: every workgroup adds the iteration's
+// fixed-point deltas (triple-buffered) to its own copy of the cluster sums in
+// LDS and computes the same new centroids and the same convergence decision.
+// Every loop is bounded, and a barrier that waits longer than two seconds sets
+// the error flag, after which no barrier waits again.
+// ---------------------------------------------------------------------------
+constexpr uint64_t kBarrierTimeoutTicks = 200000000ull;  // 2 s of the 100 MHz wall clock
+
+__device__ inline bool timed_out(uint64_t t0) { return wall_clock64() - t0 > kBarrierTimeoutTicks; }
+
+// Device-wide barrier (agent-scope fences); used once per launch.
+__device__ inline void grid_barrier(GroupBar* b, unsigned int nwg, int32_t* err) {
+  __syncthreads();
+  if (threadIdx.x == 0 && nwg > 1 &&
+      __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+    const unsigned int g = __hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const unsigned int arrived =
+        __hip_atomic_fetch_add(&b->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == nwg - 1) {
+      __hip_atomic_store(&b->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+      __hip_atomic_fetch_add(&b->gen, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      const uint64_t t0 = wall_clock64();
+      while (__hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        __builtin_amdgcn_s_sleep(2);
+        if (timed_out(t0)) {
+          __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+}
+
+// Wait until this wave's stores and atomics (flat ones count on both
+// counters) have completed; the compiler keeps memory accesses on their side.
+__device__ inline void drain_vm() { asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory"); }
+
+// Barrier of one worker's workgroups, all on one XCD.  The arrival counter
+// only grows: the e-th barrier of a launch waits until it reaches e * nwg
+// (the host zeroes it before the launch).  Arrival is a non-returning L2
+// atomic issued after this workgroup's stores have completed; the wait polls
+// the counter in L2.  With inv, every wave then invalidates at device scope,
+// so no later load is served from a line its CU's L1 kept from before
+// (another workgroup may have rewritten it since).  Without inv the caller
+// reads what other workgroups wrote only through device-scope loads
+// (load_dev), which are never served from L1.
+__device__ inline void xcd_barrier(unsigned int* count, unsigned int nwg, unsigned int& epoch,
+                                   int32_t* err, bool inv = true) {
+  drain_vm();
+  __syncthreads();
+  epoch += 1;
+  if (threadIdx.x == 0 && nwg > 1 &&
+      __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+    __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned int target = epoch * nwg;
+    const uint64_t t0 = wall_clock64();
+    while ((int)(__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
+      __builtin_amdgcn_s_sleep(1);
+      if (timed_out(t0)) {
+        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+    }
+  }
+  __syncthreads();
+  if (inv) asm volatile("buffer_inv sc1" ::: "memory");
+}
+
+// Device-scope loads (never served from L1).
+__device__ inline unsigned long long load_dev(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline int load_dev(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline double load_dev(const double* p) {
+  return __longlong_as_double((long long)load_dev(reinterpret_cast<const unsigned long long*>(p)));
+}
+
+// wave_chunked_sum through device-scope loads (same order, same result).
+__device__ inline double wave_chunked_sum_dev(const double* v, int64_t cnt) {
+  const int lane = threadIdx.x & 63;
+  const int64_t cs = (cnt + 63) / 64;
+  const int64_t lo = min(cnt, (int64_t)lane * cs), hi = min(cnt, lo + cs);
+  double tot = 0.0;
+  for (int64_t q = lo; q < hi; ++q) tot += load_dev(v + q);
+  double total = 0.0;
+  for (int l = 0; l < 64; ++l) total += __shfl(tot, l, 64);
+  return total;
+}
+
+__device__ inline void sample_range(const RoundArgs& r, int w, uint32_t purpose, uint64_t g,
+                                    int64_t sj, int64_t p0, int64_t p1, bool vec) {
+  const FeistelKey fk = feistel_key((uint64_t)r.m, r.seed, (uint32_t)w, purpose, g);
+  float* Sj = const_cast<float*>(r.as.S) + w * r.as.S_stride;
+  for (int64_t base = p0; base < p1; base += kWG)
+    sample_block(r.X, r.n, fk, sj, base, nullptr, Sj, r.cp, vec);
+}
+
+// Norm of every centroid row in LDS (FP64, one rounding): same arithmetic as
+// job_init_one / finalize_job.
+template <int NP>
+__device__ inline void lds_norms(const float* sC, float* sCn, int k) {
+  for (int j = threadIdx.x; j < k; j += kWG) {
+    double q = 0.0;
+    for (int d = 0; d < NP; ++d) q += (double)sC[j * NP + d] * (double)sC[j * NP + d];
+    sCn[j] = (float)q;
+  }
+}
+
+size_t __host__ __device__ inline round_assign_bytes(int cp, int k) {
+  const size_t base = (((size_t)k * cp + k) * 4 + 15) / 16 * 16;
+  return base + (size_t)k * cp * 8 + ((size_t)k * 4 + 15) / 16 * 16;
+}
+
+template <int NP>
+__global__ __launch_bounds__(kWG, 4) void k_round(const RoundArgs* __restrict__ rp) {
+  constexpr int PPL = NP <= 32 ? 2 : 1;
+  const RoundArgs& r = *rp;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int k = r.k, n = r.n;
+  // LDS: [assign region: centroids sC, norms sCn, delta sums, counts]
+  //      [tot: k*NP int64][tcnt: k int32][sI: k*NP incumbent][sIdeg: k]
+  float* sC = reinterpret_cast<float*>(smem);
+  float* sCn = sC + k * NP;
+  long long* tot = reinterpret_cast<long long*>(smem + round_assign_bytes(NP, k));
+  int* tcnt = reinterpret_cast<int*>(tot + k * NP);
+  float* sI = reinterpret_cast<float*>(reinterpret_cast<unsigned char*>(tcnt) + ((size_t)k * 4 + 15) / 16 * 16);
+  uint8_t* sIdeg = reinterpret_cast<uint8_t*>(sI + k * NP);
+  __shared__ unsigned int sh_slot;
+  __shared__ double sh_f;
+
+  // ---- registration on this workgroup's XCD, one device-wide barrier ----
+  unsigned int xcc;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
+  xcc &= (kMaxXcd - 1);
+  if (threadIdx.x == 0)
+    sh_slot = __hip_atomic_fetch_add(&r.reg[xcc], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  grid_barrier(r.gbar, gridDim.x, r.err);
+  const unsigned int slot = sh_slot;
+  // every workgroup checks the whole placement, so all of them agree to stop
+  for (int x = 0; x < kMaxXcd; ++x) {
+    const int got = (int)__hip_atomic_load(&r.reg[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (got < r.xcd_nw[x]) {
+      if (threadIdx.x == 0) __hip_atomic_store(r.err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return;
+    }
+  }
+  const int nx = (int)__hip_atomic_load(&r.reg[xcc], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const int nw = r.xcd_nw[xcc];
+  if (nw == 0) return;
+  // split the nx workgroups: one per worker, the rest in proportion to chunks
+  const int32_t* wl = r.xcd_workers + (int64_t)xcc * r.W;
+  int64_t ctot = 0;
+  for (int i = 0; i < nw; ++i) ctot += (r.s[wl[i]] + kWG - 1) / kWG;
+  ctot = max(ctot, (int64_t)1);
+  const int64_t R = nx - nw;
+  int64_t given = 0;
+  for (int i = 0; i < nw; ++i) given += R * ((r.s[wl[i]] + kWG - 1) / kWG) / ctot;
+  const int64_t left = R - given;
+  int w = -1, rank = 0, nwg = 0;
+  {
+    int64_t cum = 0;
+    for (int i = 0; i < nw; ++i) {
+      const int64_t ci = (r.s[wl[i]] + kWG - 1) / kWG;
+      // no more workgroups than chunks; surplus workgroups leave at once
+      const int64_t gi = max((int64_t)1, min(ci, 1 + R * ci / ctot + (i < left ? 1 : 0)));
+      if ((int64_t)slot >= cum && (int64_t)slot < cum + gi) {
+        w = wl[i];
+        rank = (int)(slot - cum);
+        nwg = (int)gi;
+      }
+      cum += gi;
+    }
+  }
+  if (w < 0) return;  // cannot happen: the groups cover all nx slots
+  const bool leader = rank == 0;
+  const int64_t sj = r.s[w];
+  const int64_t nch = (sj + kWG - 1) / kWG;
+  // contiguous chunk ranges in units of PPL chunks (one assignment loop step)
+  const int64_t units = (nch + PPL - 1) / PPL;
+  const int64_t per = (units + nwg - 1) / nwg * PPL;
+  const int64_t c0 = min(nch, (int64_t)rank * per), c1 = min(nch, c0 + per);
+  const int64_t p0 = c0 * kWG, p1 = min(sj, c1 * kWG);
+  unsigned int* bar = &r.bar[w].count;
+  unsigned int epoch = 0;
+  const bool vec = (((uintptr_t)r.X & 15) == 0) && (n % 4 == 0);
+  const int64_t mc = r.as.max_chunks;
+  double* tf3 = r.tf3 + (int64_t)w * 3 * mc;
+  unsigned long long* dl3 = r.delta + (int64_t)w * 3 * k * NP;
+  int32_t* dc3 = r.dcnt + (int64_t)w * 3 * k;
+
+  // the incumbent, kept in this workgroup's LDS
+  for (int e = threadIdx.x; e < k * NP; e += kWG) {
+    const int j = e / NP, d = e - j * NP;
+    sI[e] = d < n ? r.Cinc[((int64_t)w * k + j) * n + d] : 0.f;
+  }
+  for (int j = threadIdx.x; j < k; j += kWG) sIdeg[j] = r.deg_inc[(int64_t)w * k + j];
+  {  // the assignment's LDS sums start at zero and are left at zero by every flush
+    unsigned long long* lacc =
+        reinterpret_cast<unsigned long long*>(smem + (((size_t)k * NP + k) * 4 + 15) / 16 * 16);
+    for (int e = threadIdx.x; e < k * NP; e += kWG) lacc[e] = 0ull;
+    int* lcnt = reinterpret_cast<int*>(lacc + k * NP);
+    for (int j = threadIdx.x; j < k; j += kWG) lcnt[j] = 0;
+  }
+  double fhat = r.fhat[w];
+  __syncthreads();
+
+  // ---- re-evaluation after a size change (Algorithm 1; Section 4.2) ----
+  if (r.recalc[w]) {
+    sample_range(r, w, 4u /* RECALC */, (uint64_t)r.t, sj, p0, p1, vec);
+    for (int e = threadIdx.x; e < k * NP; e += kWG) sC[e] = sI[e];
+    __syncthreads();
+    lds_norms<NP>(sC, sCn, k);
+    __syncthreads();
+    assign_range<NP, PPL, false>(r.as, w, p0, p1, 0, smem, true, tf3 + 2 * mc);
+    xcd_barrier(bar, nwg, epoch, r.err);
+    if (threadIdx.x < 64) {
+      const double f = wave_chunked_sum(tf3 + 2 * mc, nch);
+      if (threadIdx.x == 0) sh_f = f;
+    }
+    __syncthreads();
+    fhat = sh_f;
+    if (leader && threadIdx.x == 0) {
+      r.fhat[w] = fhat;
+      r.recalc_f[w] = fhat;
+    }
+  }
+
+  int ig = 0;  // Lloyd iterations of this launch (selects the triple buffers)
+  for (int q = 0; q < r.passes_p; ++q) {
+    const uint64_t g = (uint64_t)r.t * r.passes_p + q;
+    sample_range(r, w, 2u /* SAMPLE */, g, sj, p0, p1, vec);
+    int ntodo = 0;
+    for (int j = 0; j < k; ++j) ntodo += sIdeg[j] ? 1 : 0;
+    if (ntodo > 0) {
+      // K-means++ for the degenerate centroids, on the global working copy
+      const KppArgs& ka = r.ka;
+      if (leader) {
+        float* Cp = r.Cp + (int64_t)w * k * NP;
+        for (int e = threadIdx.x; e < k * NP; e += kWG) Cp[e] = sI[e];
+        for (int j = threadIdx.x; j < k; j += kWG) r.deg_work[(int64_t)w * k + j] = sIdeg[j];
+        if (threadIdx.x == 0) const_cast<uint64_t*>(ka.gs)[w] = g;
+        drain_vm();
+        __syncthreads();
+        kpp_setup_job(ka, w);
+      }
+      xcd_barrier(bar, nwg, epoch, r.err);
+      for (int64_t tl = c0; tl < c1; ++tl) kpp_init_tile(ka, w, tl);
+      xcd_barrier(bar, nwg, epoch, r.err);
+      for (int step = 0; step < ntodo; ++step) {
+        if (leader && threadIdx.x < 64) kpp_step_job(ka, w);
+        xcd_barrier(bar, nwg, epoch, r.err);
+        for (int64_t tl = c0; tl < c1; ++tl) kpp_pot_tile(ka, w, tl);
+        xcd_barrier(bar, nwg, epoch, r.err);
+      }
+      if (leader && threadIdx.x < 64) kpp_step_job(ka, w);  // commits the last step
+      xcd_barrier(bar, nwg, epoch, r.err);
+      const float* Cp = r.Cp + (int64_t)w * k * NP;
+      for (int e = threadIdx.x; e < k * NP; e += kWG) sC[e] = Cp[e];
+    } else {
+      for (int e = threadIdx.x; e < k * NP; e += kWG) sC[e] = sI[e];
+    }
+    for (int e = threadIdx.x; e < k * NP; e += kWG) tot[e] = 0;
+    for (int j = threadIdx.x; j < k; j += kWG) tcnt[j] = 0;
+    __syncthreads();
+    lds_norms<NP>(sC, sCn, k);
+    __syncthreads();
+
+    // ---- Lloyd ----
+    double f_prev = 0.0;
+    for (int it = 0; it <= r.max_iter; ++it, ++ig) {
+      const int b = ig % 3;
+      assign_range<NP, PPL, true>(r.as, w, p0, p1, it == 0 ? 1 : 0, smem, true, tf3 + b * mc,
+                                  dl3 + (int64_t)b * k * NP, dc3 + b * k);
+      if (leader) {  // clear the buffer of the next iteration (last read two barriers ago)
+        const int bn = (b + 1) % 3;
+        for (int e = threadIdx.x; e < k * NP; e += kWG)
+          __hip_atomic_store(dl3 + (int64_t)bn * k * NP + e, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int j = threadIdx.x; j < k; j += kWG)
+          __hip_atomic_store(dc3 + bn * k + j, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      xcd_barrier(bar, nwg, epoch, r.err, false);
+      // every arrival's atomics and stores are complete in L2
+      for (int e = threadIdx.x; e < k * NP; e += kWG) tot[e] += (long long)load_dev(dl3 + (int64_t)b * k * NP + e);
+      for (int j = threadIdx.x; j < k; j += kWG) tcnt[j] += load_dev(dc3 + b * k + j);
+      if (threadIdx.x < 64) {
+        const double f = wave_chunked_sum_dev(tf3 + b * mc, nch);
+        if (threadIdx.x == 0) sh_f = f;
+      }
+      __syncthreads();
+      const double f = sh_f;
+      const bool stop = (it > 0 && f_prev - f <= r.tol * f) || !isfinite(f) || it >= r.max_iter;
+      if (!stop) {
+        for (int e = threadIdx.x; e < k * NP; e += kWG) {
+          const int j = e / NP, d = e - j * NP;
+          if (tcnt[j] > 0) sC[e] = (float)(((double)tot[e] * r.inv_scale[d]) / (double)tcnt[j]);
+        }
+        __syncthreads();
+        lds_norms<NP>(sC, sCn, k);
+        __syncthreads();
+        f_prev = f;
+        continue;
+      }
+      // stop: degenerate flags; acceptance on a strict improvement
+      const bool accept = f < fhat;
+      int nd = 0;
+      for (int j = 0; j < k; ++j) nd += tcnt[j] == 0 ? 1 : 0;
+      if (accept) {
+        for (int e = threadIdx.x; e < k * NP; e += kWG) sI[e] = sC[e];
+        for (int j = threadIdx.x; j < k; j += kWG) sIdeg[j] = tcnt[j] == 0 ? 1 : 0;
+        if (leader) {
+          for (int e = threadIdx.x; e < k * n; e += kWG) {
+            const int j = e / n, d = e - j * n;
+            r.Cinc[(int64_t)w * k * n + e] = sC[j * NP + d];
+          }
+          for (int j = threadIdx.x; j < k; j += kWG)
+            r.deg_inc[(int64_t)w * k + j] = tcnt[j] == 0 ? 1 : 0;
+          if (threadIdx.x == 0) r.fhat[w] = f;
+        }
+        fhat = f;
+      }
+      if (leader && threadIdx.x == 0) {
+        PassOut o;
+        o.accepted = accept ? 1 : 0;
+        o.iters = it;
+        o.ndeg = nd;
+        o.pad_ = 1;  // marks the pass as run
+        o.f = f;
+        r.out[(int64_t)w * r.passes_p + q] = o;
+      }
+      __syncthreads();
+      ++ig;
+      break;
+    }
+  }
+}
+
+// XCD id of each workgroup of a grid (the hardware's workgroup placement).
+__global__ __launch_bounds__(64) void k_xcd_probe(uint32_t* __restrict__ out) {
+  unsigned int x;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(x));
+  if (threadIdx.x == 0) out[blockIdx.x] = x & (kMaxXcd - 1);
+}
+
+template <int NP>
+hipError_t round_capacity_np(size_t lds, int* blocks) {
+  int per_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_round<NP>, kWG, lds);
+  if (e != hipSuccess) return e;
+  int dev = 0, cus = 0;
+  e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  *blocks = per_cu * cus;
+  return hipSuccess;
+}
+
+template <int NP>
+hipError_t launch_round_np(hipStream_t st, const RoundArgs* r_dev, int grid, size_t lds) {
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_round<NP>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  const RoundArgs* p = r_dev;
+  void* args[] = {&p};
+  return hipLaunchCooperativeKernel((const void*)k_round<NP>, dim3(grid), dim3(kWG), args,
+                                    (unsigned int)lds, st);
 }
 
 template <int NP>
@@ -868,14 +1355,10 @@ hipError_t launch_sample(hipStream_t st, const float* X, int64_t m, int32_t n, i
                          int64_t max_s, const int64_t* s, const uint64_t* rkeys, int32_t* idx,
                          int64_t idx_stride, float* S, int64_t S_stride, int32_t ld) {
   const dim3 grid((unsigned)((max_s + kWG - 1) / kWG), (unsigned)njobs);
-  const bool vec = (n % 4 == 0) && (ld % 4 == 0) && (((uintptr_t)X & 15) == 0) &&
-                   (S == nullptr || ((uintptr_t)S & 15) == 0) && (S_stride % 4 == 0);
-  if (vec)
-    hipLaunchKernelGGL(k_sample<true>, grid, dim3(kWG), 0, st, X, m, n, s, rkeys, idx, idx_stride,
-                       S, S_stride, ld);
-  else
-    hipLaunchKernelGGL(k_sample<false>, grid, dim3(kWG), 0, st, X, m, n, s, rkeys, idx,
-                       idx_stride, S, S_stride, ld);
+  const int vec = ((n % 4 == 0) && (ld % 4 == 0) && (((uintptr_t)X & 15) == 0) &&
+                   (S == nullptr || ((uintptr_t)S & 15) == 0) && (S_stride % 4 == 0)) ? 1 : 0;
+  hipLaunchKernelGGL(k_sample, grid, dim3(kWG), 0, st, X, m, n, s, rkeys, idx, idx_stride, S,
+                     S_stride, ld, vec);
   return hipGetLastError();
 }
 
@@ -977,6 +1460,50 @@ hipError_t launch_copy_incumbent(hipStream_t st, const float* Cinc, const uint8_
   hipLaunchKernelGGL(k_copy_incumbent, dim3(njobs), dim3(kWG), 0, st, Cinc, deg_inc, n, cp, k, Cp,
                      deg_work);
   return hipGetLastError();
+}
+
+size_t round_lds_bytes(int32_t cp, int32_t k) {
+  return round_assign_bytes(cp, k) + (size_t)k * cp * 8 + ((size_t)k * 4 + 15) / 16 * 16 +
+         (size_t)k * cp * 4 + ((size_t)k + 15) / 16 * 16;
+}
+
+#define BM_ROUND_SWITCH(CALL)      \
+  switch (cp) {                    \
+    case 4: return CALL(4);        \
+    case 8: return CALL(8);        \
+    case 12: return CALL(12);      \
+    case 16: return CALL(16);      \
+    case 20: return CALL(20);      \
+    case 24: return CALL(24);      \
+    case 28: return CALL(28);      \
+    case 32: return CALL(32);      \
+    case 36: return CALL(36);      \
+    case 40: return CALL(40);      \
+    case 44: return CALL(44);      \
+    case 48: return CALL(48);      \
+    case 52: return CALL(52);      \
+    case 56: return CALL(56);      \
+    case 60: return CALL(60);      \
+    case 64: return CALL(64);      \
+    default: return hipErrorInvalidValue; \
+  }
+
+hipError_t launch_xcd_probe(hipStream_t st, uint32_t* out, int32_t grid) {
+  hipLaunchKernelGGL(k_xcd_probe, dim3(grid), dim3(64), 0, st, out);
+  return hipGetLastError();
+}
+
+hipError_t round_capacity(int32_t cp, size_t lds, int* blocks) {
+#define BM_CAP(NPV) round_capacity_np<NPV>(lds, blocks)
+  BM_ROUND_SWITCH(BM_CAP)
+#undef BM_CAP
+}
+
+hipError_t launch_round(hipStream_t st, const RoundArgs* r_dev, int32_t cp, int32_t grid,
+                        size_t lds) {
+#define BM_LR(NPV) launch_round_np<NPV>(st, r_dev, grid, lds)
+  BM_ROUND_SWITCH(BM_LR)
+#undef BM_LR
 }
 
 hipError_t launch_kpp_setup(hipStream_t st, const KppArgs& a, int32_t njobs) {

@@ -372,16 +372,22 @@ def test_bigmeans_uniform_sizes_matches_oracle(dev, api):
     assert g["improvements"] >= P["workers"]
 
 
-def test_bigmeans_batched_equals_plain(dev, api):
+@pytest.mark.parametrize("policy,seed", [(2, 11), (0, 12), (3, 13)])
+def test_bigmeans_execution_modes_identical(dev, api, policy, seed):
+    # persistent rounds (1), one launch per Lloyd step (2) and one worker per
+    # launch (0) compute the same arithmetic: results are bitwise identical
     X = _data("noisy28", 50_000, 2)
-    P = dict(k=20, workers=5, rounds_T=2, passes_p=3, s_min=1000, s_max=6000, seed=11,
-             size_policy=2)
-    say("bigmeans batched vs plain", X.shape, P)
-    a = api.bigmeans_run(to_dev(X, dev), api.RunParams(batched=True, **P))
-    b = api.bigmeans_run(to_dev(X, dev), api.RunParams(batched=False, **P))
-    assert a["f_full"] == b["f_full"] and a["s_opt"] == b["s_opt"]
-    assert a["best_worker"] == b["best_worker"] and a["lloyd_dists"] == b["lloyd_dists"]
-    assert np.array_equal(a["C_best"].cpu().numpy(), b["C_best"].cpu().numpy())
+    P = dict(k=20, workers=5, rounds_T=3, passes_p=3, s_min=1000, s_max=6000, seed=seed,
+             size_policy=policy)
+    say("bigmeans modes", X.shape, P)
+    runs = [api.bigmeans_run(to_dev(X, dev), api.RunParams(batched=b, **P)) for b in (1, 2, 0)]
+    a = runs[0]
+    for b in runs[1:]:
+        assert a["f_full"] == b["f_full"] and a["s_opt"] == b["s_opt"]
+        assert a["best_worker"] == b["best_worker"] and a["lloyd_dists"] == b["lloyd_dists"]
+        assert a["improvements"] == b["improvements"]
+        assert np.array_equal(a["C_best"].cpu().numpy(), b["C_best"].cpu().numpy())
+        assert np.array_equal(a["Y"].cpu().numpy(), b["Y"].cpu().numpy())
 
 
 def test_bigmeans_bins_policy_runs(dev, api):
