@@ -32,6 +32,8 @@ namespace {
 constexpr int kNumStage = 16;
 constexpr size_t kStageBytes = 256 * 1024;
 constexpr int kNBins = 5;
+constexpr int kMaxDim = 4096;            // largest point dimension
+constexpr size_t kMaxLds = 160 * 1024;   // LDS of one compute unit
 
 int round_up4(int n) { return (n + 3) & ~3; }
 
@@ -55,7 +57,7 @@ struct bm_ctx {
 
   // device workspace
   DevBuf S, idx, labels, Cp, cn, Cinc, deg_work, deg_inc, fhat, acc, cnt, tf, tnear, js, sizes, tile_job, tile_idx, rkeys, seed_worker, absmax, scale, inv_scale,
-      fjob, nearjob, D, Dt, ks, todo, picks, gs, rflags, wgmap, rargs, rres, bars, rwork;
+      fjob, nearjob, D, Dt, ks, todo, picks, gs, rflags, wgmap, rargs, rres, bars, rwork, labels2;
   int xcd_cap = 0;                  // grid size the XCD layout below was measured for
   int xcd_wgs[bm::kMaxXcd] = {0};   // workgroups of that grid on each XCD
   bool round_ok = true;             // the persistent round kernel fits this device
@@ -381,6 +383,25 @@ int lloyd_batch(bm_ctx* c, const BatchView& b, int max_iter, double tol, int32_t
     f.fhat = P<double>(c->fhat) + first;
   }
 
+  // Wide points: assignment q writes its labels to L[q % 2] (L[0] = labels,
+  // L[1] = a second buffer with the same layout) and a separate kernel adds
+  // the label changes L[(q+1) % 2] -> L[q % 2] to the fixed-point sums.
+  const bool wide = cp > bm::kMaxRegDim;
+  int32_t* lab2 = nullptr;
+  if (wide) {
+    if (J > 1 && lab_stride != c->max_s) return c->fail(BM_E_STATE, "label layout");
+    const size_t need = (size_t)(J - 1) * lab_stride + (size_t)c->max_s;
+    if (c->labels2.bytes < need * sizeof(int32_t)) {
+      HIP_TRY(c, hipStreamSynchronize(c->stream));
+      BM_TRY(dev_alloc(c, c->labels2, (size_t)c->max_jobs * c->max_s * sizeof(int32_t)));
+    }
+    lab2 = P<int32_t>(c->labels2) + (int64_t)first * c->max_s;
+    if (J == 1) lab2 = P<int32_t>(c->labels2);
+  }
+  int32_t* const lab_arr[2] = {labels, lab2};
+  int64_t max_size = 0;
+  for (int64_t v : b.sizes) max_size = std::max(max_size, v);
+
   // Each job makes at most max_iter + 1 assignments.  Launch a few
   // iterations between checks of the job states; after each check the tile
   // map keeps only the jobs that still iterate.
@@ -400,9 +421,21 @@ int lloyd_batch(bm_ctx* c, const BatchView& b, int max_iter, double tol, int32_t
     }
     for (int q = 0; q < todo; ++q) {
       if (c->prof) HIP_TRY(c, hipEventRecord(c->pev[2 * q], c->stream));
-      HIP_TRY(c, bm::launch_assign(c->stream, a, tm.total, true));
+      if (wide) {
+        const int qa = launched + q;  // assignment index of this launch
+        a.labels = lab_arr[qa & 1];
+        HIP_TRY(c, bm::launch_assign_wide(c->stream, a, tm.total, true));
+        HIP_TRY(c, bm::launch_update_wide(c->stream, b.S, b.S_stride, b.ld, b.n, cp, k, a.s, js, J,
+                                          max_size, qa == 0 ? nullptr : lab_arr[(qa + 1) & 1],
+                                          lab_arr[qa & 1], lab_stride, acc, cnt, a.scale));
+      } else {
+        HIP_TRY(c, bm::launch_assign(c->stream, a, tm.total, true));
+      }
       if (c->prof) HIP_TRY(c, hipEventRecord(c->pev[2 * q + 1], c->stream));
-      HIP_TRY(c, bm::launch_finalize(c->stream, f, J));
+      if (wide)
+        HIP_TRY(c, bm::launch_finalize_wide(c->stream, f, J));
+      else
+        HIP_TRY(c, bm::launch_finalize(c->stream, f, J));
     }
     launched += todo;
     BM_TRY(readback(c, js, J * sizeof(JobState), hs.data()));
@@ -431,6 +464,13 @@ int lloyd_batch(bm_ctx* c, const BatchView& b, int max_iter, double tol, int32_t
     }
     if (!any) {
       if (out) *out = hs;
+      if (wide) {  // final labels of a job whose last assignment was odd are in L[1]
+        for (int j = 0; j < J; ++j)
+          if (hs[j].iter & 1)
+            HIP_TRY(c, hipMemcpyAsync(labels + (int64_t)j * lab_stride, lab2 + (int64_t)j * lab_stride,
+                                      (size_t)b.sizes[j] * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                                      c->stream));
+      }
       break;
     }
     if (launched >= max_iter + 1) return c->fail(BM_E_STATE, "Lloyd did not stop after %d steps", launched);
@@ -477,7 +517,10 @@ int objective_batch(bm_ctx* c, const BatchView& b, int32_t* labels, int64_t lab_
   a.cnt = nullptr;
   a.scale = nullptr;
   a.st = nullptr;
-  HIP_TRY(c, bm::launch_assign(c->stream, a, tm.total, false));
+  if (cp > bm::kMaxRegDim)
+    HIP_TRY(c, bm::launch_assign_wide(c->stream, a, tm.total, false));
+  else
+    HIP_TRY(c, bm::launch_assign(c->stream, a, tm.total, false));
   HIP_TRY(c, bm::launch_reduce_f(c->stream, P<double>(c->tf), a.tnear,
                                  P<int64_t>(c->sizes) + first, (int32_t)max_chunks, J,
                                  P<double>(c->fjob) + first,
@@ -569,31 +612,43 @@ int xcd_layout(bm_ctx* c, int cap) {
   return BM_OK;
 }
 
-// One round of Algorithm 1 for all workers in one cooperative launch.  Workers
-// are placed on XCDs largest first, each on the XCD whose load per workgroup
-// grows least (at most one worker per workgroup of an XCD).
+// One round of Algorithm 1 for all workers in one cooperative launch.
+//
+// Placement: a worker's Lloyd iteration costs about F + L * (assignment steps
+// of its busiest workgroup), and it runs about `iters[w]` of them (taken from
+// its previous round).  Workers go to XCDs largest predicted work first, each
+// to the XCD with the least work per workgroup; then each XCD hands its spare
+// workgroups one at a time to the worker with the largest predicted time.
 int round_persistent(bm_ctx* c, const float* X, const bm_params& p, int t,
                      const std::vector<int64_t>& sizes, const std::vector<int32_t>& recalc,
-                     RoundResult* res) {
+                     const std::vector<double>& iters, RoundResult* res) {
   const int W = p.workers, k = p.k, n = p.n, cp = round_up4(n);
   const size_t lds = bm::round_lds_bytes(cp, k);
   int cap = 0;
   HIP_TRY(c, bm::round_capacity(cp, lds, &cap));
   if (cap < W) return kRoundNoFit;
   BM_TRY(xcd_layout(c, cap));
+  const int ppl = cp <= 32 ? 2 : 1;
+  constexpr double kF = 20.0, kL = 16.0;  // relative costs (microseconds, measured)
+  std::vector<int64_t> units(W);
+  std::vector<double> work(W);
+  for (int w = 0; w < W; ++w) {
+    const int64_t nch = (sizes[w] + bm::kWG - 1) / bm::kWG;
+    units[w] = std::max<int64_t>(1, (nch + ppl - 1) / ppl);
+    work[w] = std::max(1.0, iters[w]) * (double)units[w];
+  }
   std::vector<int> order(W);
   for (int w = 0; w < W; ++w) order[w] = w;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int a, int b) { return sizes[a] > sizes[b]; });
-  std::vector<int32_t> xnw(bm::kMaxXcd, 0), xw((size_t)bm::kMaxXcd * W, 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+  std::vector<int32_t> xnw(bm::kMaxXcd, 0), xw((size_t)bm::kMaxXcd * W, 0),
+      xg((size_t)bm::kMaxXcd * W, 0);
   std::vector<double> load(bm::kMaxXcd, 0.0);
   for (int w : order) {
-    const double ch = (double)((sizes[w] + bm::kWG - 1) / bm::kWG);
     int best = -1;
     double best_v = 0.0;
     for (int x = 0; x < bm::kMaxXcd; ++x) {
       if (xnw[x] >= c->xcd_wgs[x]) continue;
-      const double v = (load[x] + ch) / (double)c->xcd_wgs[x];
+      const double v = (load[x] + work[w]) / (double)c->xcd_wgs[x];
       if (best < 0 || v < best_v) {
         best = x;
         best_v = v;
@@ -602,7 +657,31 @@ int round_persistent(bm_ctx* c, const float* X, const bm_params& p, int t,
     if (best < 0) return kRoundNoFit;
     xw[(size_t)best * W + xnw[best]] = w;
     xnw[best] += 1;
-    load[best] += ch;
+    load[best] += work[w];
+  }
+  auto t_of = [&](int w, int64_t g) {
+    return std::max(1.0, iters[w]) * (kF + kL * (double)((units[w] + g - 1) / g));
+  };
+  for (int x = 0; x < bm::kMaxXcd; ++x) {
+    const int nw = xnw[x];
+    if (nw == 0) continue;
+    int32_t* g = &xg[(size_t)x * W];
+    const int32_t* wl = &xw[(size_t)x * W];
+    for (int i = 0; i < nw; ++i) g[i] = 1;
+    for (int spare = c->xcd_wgs[x] - nw; spare > 0; --spare) {
+      int bi = -1;
+      double bt = 0.0;
+      for (int i = 0; i < nw; ++i) {
+        if (g[i] >= units[wl[i]]) continue;  // one more workgroup would idle
+        const double tw = t_of(wl[i], g[i]);
+        if (bi < 0 || tw > bt) {
+          bi = i;
+          bt = tw;
+        }
+      }
+      if (bi < 0) break;
+      g[bi] += 1;
+    }
   }
   const int64_t mc = c->max_chunks;
   // work buffer: [reg kMaxXcd][grid barrier][W barriers][delta W*3*k*cp][dcnt W*3*k] | [tf3 W*3*mc]
@@ -611,7 +690,7 @@ int round_persistent(bm_ctx* c, const float* X, const bm_params& p, int t,
   const size_t off_dcnt = off_delta + (size_t)W * 3 * k * cp * sizeof(unsigned long long);
   const size_t off_tf3 = (off_dcnt + (size_t)W * 3 * k * sizeof(int32_t) + 255) / 256 * 256;
   const size_t work_bytes = off_tf3 + (size_t)W * 3 * mc * sizeof(double);
-  const size_t map_bytes = (size_t)bm::kMaxXcd * (W + 1) * sizeof(int32_t);
+  const size_t map_bytes = (size_t)bm::kMaxXcd * (2 * W + 1) * sizeof(int32_t);
   const size_t rres_bytes = 16 + (size_t)W * sizeof(double) + (size_t)W * p.passes_p * sizeof(bm::PassOut);
   if (c->rwork.bytes < work_bytes || c->wgmap.bytes < map_bytes || c->rres.bytes < rres_bytes) {
     HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -622,6 +701,7 @@ int round_persistent(bm_ctx* c, const float* X, const bm_params& p, int t,
   int32_t* d_map = P<int32_t>(c->wgmap);
   BM_TRY(upload(c, d_map, xnw.data(), bm::kMaxXcd * sizeof(int32_t)));
   BM_TRY(upload(c, d_map + bm::kMaxXcd, xw.data(), (size_t)bm::kMaxXcd * W * sizeof(int32_t)));
+  BM_TRY(upload(c, d_map + bm::kMaxXcd * (1 + W), xg.data(), (size_t)bm::kMaxXcd * W * sizeof(int32_t)));
   BM_TRY(upload(c, P<int64_t>(c->sizes), sizes.data(), W * sizeof(int64_t)));
   BM_TRY(upload(c, P<int32_t>(c->rflags), recalc.data(), W * sizeof(int32_t)));
   unsigned char* rr = P<unsigned char>(c->rres);
@@ -647,6 +727,7 @@ int round_persistent(bm_ctx* c, const float* X, const bm_params& p, int t,
   r.recalc = P<int32_t>(c->rflags);
   r.xcd_nw = d_map;
   r.xcd_workers = d_map + bm::kMaxXcd;
+  r.xcd_g = d_map + bm::kMaxXcd * (1 + W);
   r.reg = reinterpret_cast<unsigned int*>(wk);
   r.gbar = reinterpret_cast<bm::GroupBar*>(wk + off_gbar);
   r.bar = reinterpret_cast<bm::GroupBar*>(wk + off_bar);
@@ -736,10 +817,15 @@ int check_prec(bm_ctx* c, int prec) {
   return BM_OK;
 }
 
-int check_dim(bm_ctx* c, int n) {
+int check_dim(bm_ctx* c, int n, int k) {
   if (n < 1) return c->fail(BM_E_ARG, "n must be >= 1");
-  if (round_up4(n) > bm::kMaxRegDim)
-    return c->fail(BM_E_ARG, "n = %d exceeds the supported dimension %d", n, bm::kMaxRegDim);
+  if (n > kMaxDim) return c->fail(BM_E_ARG, "n = %d exceeds the supported dimension %d", n, kMaxDim);
+  if (k < 1) return c->fail(BM_E_ARG, "k must be >= 1");
+  // LDS of the fixed-point sums: k x cp (narrow) or k x 64 (wide) int64
+  const int cp = round_up4(n);
+  const size_t lds = cp > bm::kMaxRegDim ? bm::update_wide_lds(k)
+                                         : (size_t)k * cp * 12 + (size_t)k * 8 + 64;
+  if (lds > kMaxLds) return c->fail(BM_E_ARG, "k = %d is too large for n = %d", k, n);
   return BM_OK;
 }
 
@@ -809,7 +895,7 @@ int validate_params(bm_ctx* c, const bm_params* p) {
   if (p->size_policy == BM_SIZE_FIXED && p->s_min != p->s_max)
     return c->fail(BM_E_ARG, "FIXED size policy needs s_min == s_max");
   BM_TRY(check_prec(c, p->prec));
-  BM_TRY(check_dim(c, p->n));
+  BM_TRY(check_dim(c, p->n, p->k));
   return BM_OK;
 }
 
@@ -864,7 +950,7 @@ BM_API void bm_destroy(bm_ctx* c) {
                     &c->rkeys,    &c->seed_worker, &c->absmax, &c->scale,   &c->inv_scale,
                     &c->fjob,     &c->nearjob, &c->D,         &c->Dt,
                     &c->ks,       &c->todo,    &c->picks,    &c->gs,        &c->rflags,
-                    &c->wgmap,    &c->rargs,   &c->rres,     &c->bars, &c->rwork};
+                    &c->wgmap,    &c->rargs,   &c->rres,     &c->bars, &c->rwork, &c->labels2};
   for (DevBuf* b : bufs) dev_free(*b);
   for (int i = 0; i < kNumStage; ++i) {
     if (c->stage[i]) (void)hipHostFree(c->stage[i]);
@@ -912,7 +998,7 @@ BM_API int bm_seed(bm_ctx* c, const float* S, int64_t s, int32_t n, int32_t k, f
   if (!S || !C || !degenerate) return c->fail(BM_E_ARG, "S, C and degenerate are required");
   if (k < 1 || s < k || n < 1) return c->fail(BM_E_ARG, "need 1 <= k <= s, n >= 1");
   if (n_candidates < 1 || n_candidates > 3) return c->fail(BM_E_ARG, "n_candidates must be 1..3");
-  BM_TRY(check_dim(c, n));
+  BM_TRY(check_dim(c, n, k));
   HIP_TRY(c, hipSetDevice(c->device));
   BM_TRY(ensure(c, s, n, k, 1));
   const int cp = round_up4(n);
@@ -944,7 +1030,7 @@ BM_API int bm_lloyd(bm_ctx* c, const float* S, int64_t s, int32_t n, int32_t k, 
   if (!S || !C || !f_out) return c->fail(BM_E_ARG, "S, C and f_out are required");
   if (k < 1 || s < 1 || max_iter < 0 || !(tol >= 0.0)) return c->fail(BM_E_ARG, "need k >= 1, s >= 1, max_iter >= 0, tol >= 0");
   BM_TRY(check_prec(c, prec));
-  BM_TRY(check_dim(c, n));
+  BM_TRY(check_dim(c, n, k));
   HIP_TRY(c, hipSetDevice(c->device));
   BM_TRY(ensure(c, s, n, k, 1));
   const int cp = round_up4(n);
@@ -979,7 +1065,7 @@ BM_API int bm_objective(bm_ctx* c, const float* X, int64_t m, int32_t n, const f
   if (!X || !C || !f_out) return c->fail(BM_E_ARG, "X, C and f_out are required");
   if (k < 1 || m < 1) return c->fail(BM_E_ARG, "need k >= 1, m >= 1");
   BM_TRY(check_prec(c, prec));
-  BM_TRY(check_dim(c, n));
+  BM_TRY(check_dim(c, n, k));
   HIP_TRY(c, hipSetDevice(c->device));
   BM_TRY(ensure(c, 1, n, k, 1));
   BM_TRY(ensure_objective(c, m));
@@ -1065,6 +1151,7 @@ BM_API int bm_bigmeans_run(bm_ctx* c, const float* X, const bm_params* params, f
   std::vector<double> fhat(W, std::numeric_limits<double>::infinity());
   BM_TRY(upload(c, c->fhat.p, fhat.data(), W * sizeof(double)));
   std::vector<int64_t> s_cur(W, -1), s_new(W, 0);
+  std::vector<double> iters_prev(W, 1.0);  // Lloyd iterations of each worker's last round
   std::vector<int32_t> bin_cur(W, 0);
   std::vector<int32_t> ndeg(W, k);
   int64_t bacc[kNBins] = {0}, bpass[kNBins] = {0};
@@ -1097,10 +1184,11 @@ BM_API int bm_bigmeans_run(bm_ctx* c, const float* X, const bm_params* params, f
     // launch (the multi-launch path below runs when it does not fit the device)
     bool round_done = false;
     std::vector<int32_t> rflag(W, 0);
+    if (t == 0) iters_prev.assign(W, 1.0);
     RoundResult rres;
-    if (p.batched == 1 && c->round_ok) {
+    if (p.batched == 1 && c->round_ok && cp <= bm::kMaxRegDim) {  // wide points: multi-launch
       for (int w = 0; w < W; ++w) rflag[w] = (std::isfinite(fhat[w]) && s_new[w] != s_cur[w]) ? 1 : 0;
-      const int rc = round_persistent(c, X, p, t, s_new, rflag, &rres);
+      const int rc = round_persistent(c, X, p, t, s_new, rflag, iters_prev, &rres);
       if (rc == kRoundNoFit) c->round_ok = false;
       else BM_TRY(rc);
       round_done = rc == BM_OK;
@@ -1111,6 +1199,8 @@ BM_API int bm_bigmeans_run(bm_ctx* c, const float* X, const bm_params* params, f
       for (int w = 0; w < W; ++w) {
         s_cur[w] = s_new[w];
         if (rflag[w]) fhat[w] = rres.recalc_f[w];
+        iters_prev[w] = 0.0;
+        for (int q = 0; q < p.passes_p; ++q) iters_prev[w] += rres.out[(size_t)w * p.passes_p + q].iters + 1;
         for (int q = 0; q < p.passes_p; ++q) {
           const bm::PassOut& o = rres.out[(size_t)w * p.passes_p + q];
           lloyd_iters += o.iters + 1;

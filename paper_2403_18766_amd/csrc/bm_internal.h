@@ -102,6 +102,20 @@ hipError_t launch_centroid_norms(hipStream_t st, const float* Cp, int32_t cp, in
                                  int32_t njobs, float* cn);
 hipError_t launch_assign(hipStream_t st, const AssignArgs& a, int32_t ntiles_total, bool sums);
 hipError_t launch_finalize(hipStream_t st, const FinalizeArgs& a, int32_t njobs);
+
+// ---- wide points, cp > kMaxRegDim (bm_wide.hip) ----
+// tile_pts must be a multiple of 256.
+hipError_t launch_assign_wide(hipStream_t st, const AssignArgs& a, int32_t ntiles, bool sums);
+// Fixed-point sums of the label changes lab_old -> lab_new (lab_old null on
+// the first assignment) for every active job.
+hipError_t launch_update_wide(hipStream_t st, const float* S, int64_t S_stride, int32_t ld,
+                              int32_t n, int32_t cp, int32_t k, const int64_t* s,
+                              const JobState* js, int32_t njobs, int64_t max_s,
+                              const int32_t* lab_old, const int32_t* lab_new, int64_t lab_stride,
+                              unsigned long long* acc, int32_t* cnt, const double* scale);
+hipError_t launch_finalize_wide(hipStream_t st, const FinalizeArgs& a, int32_t njobs);
+// LDS bytes of the wide update kernel for k clusters.
+size_t update_wide_lds(int32_t k);
 hipError_t launch_job_init(hipStream_t st, JobState* js, const int64_t* sizes, int32_t njobs,
                            int32_t k, int32_t cp, unsigned long long* acc, int32_t* cnt,
                            const float* Cp, float* cn);
@@ -163,6 +177,7 @@ struct RoundArgs {
   const int32_t* recalc;       // [W] re-evaluate the incumbent on a fresh sample first
   const int32_t* xcd_nw;       // [kMaxXcd] number of workers placed on each XCD
   const int32_t* xcd_workers;  // [kMaxXcd][W] the workers placed on each XCD
+  const int32_t* xcd_g;        // [kMaxXcd][W] workgroups of each of those workers
   unsigned int* reg;           // [kMaxXcd] registration counters (zero at launch)
   GroupBar* gbar;              // device-wide barrier (zero at launch)
   GroupBar* bar;               // [W] worker barriers (zero at launch)

@@ -30,6 +30,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "bm_device.h"
 #include "bm_internal.h"
 #include "bm_rng.h"
 
@@ -37,19 +38,8 @@ namespace bm {
 
 namespace {
 
-constexpr float kU = 5.9604644775390625e-8f;  // 2^-24
 
-__device__ inline double wave_sum_f64(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
 
-__device__ inline int wave_sum_i32(int v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
 
 // Deterministic sum over a 256-thread workgroup; result valid in thread 0.
 __device__ inline double block_sum_f64(double v, double* sh4) {
@@ -74,19 +64,6 @@ __device__ inline int block_sum_i32(int v, int* sh4) {
   return r;
 }
 
-// Deterministic sum of v[0..cnt) by one wave: lane l adds a contiguous chunk
-// in order, then the 64 chunk totals are added in lane order.  The result is
-// the same in every lane and depends only on cnt and the values.
-__device__ inline double wave_chunked_sum(const double* __restrict__ v, int64_t cnt) {
-  const int lane = threadIdx.x & 63;
-  const int64_t cs = (cnt + 63) / 64;
-  const int64_t lo = min(cnt, (int64_t)lane * cs), hi = min(cnt, lo + cs);
-  double tot = 0.0;
-  for (int64_t q = lo; q < hi; ++q) tot += v[q];
-  double total = 0.0;
-  for (int l = 0; l < 64; ++l) total += __shfl(tot, l, 64);
-  return total;
-}
 
 // min that propagates NaN from either operand.
 __device__ inline float min_nan(float a, float b) {
@@ -289,9 +266,6 @@ __global__ __launch_bounds__(kWG) void k_unpad(const float* __restrict__ Cp, int
 // ---------------------------------------------------------------------------
 typedef const double __attribute__((address_space(4)))* cdouble_p;
 
-__device__ inline long long quantize(float x, double scale) {
-  return (long long)((double)x * scale);
-}
 
 // PPL points per lane: the workgroup covers 256*PPL consecutive points per
 // step, lane t taking points base + t + 256 p.  The job's centroids and norms
@@ -1028,13 +1002,23 @@ __device__ inline double load_dev(const double* p) {
   return __longlong_as_double((long long)load_dev(reinterpret_cast<const unsigned long long*>(p)));
 }
 
-// wave_chunked_sum through device-scope loads (same order, same result).
+// wave_chunked_sum through device-scope loads (same order, same result).  Up
+// to 4 values per lane (256 chunks) are loaded together before they are added.
 __device__ inline double wave_chunked_sum_dev(const double* v, int64_t cnt) {
   const int lane = threadIdx.x & 63;
   const int64_t cs = (cnt + 63) / 64;
   const int64_t lo = min(cnt, (int64_t)lane * cs), hi = min(cnt, lo + cs);
   double tot = 0.0;
-  for (int64_t q = lo; q < hi; ++q) tot += load_dev(v + q);
+  if (cs <= 4) {
+    double t[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) t[q] = lo + q < hi ? load_dev(v + lo + q) : 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (lo + q < hi) tot += t[q];
+  } else {
+    for (int64_t q = lo; q < hi; ++q) tot += load_dev(v + q);
+  }
   double total = 0.0;
   for (int l = 0; l < 64; ++l) total += __shfl(tot, l, 64);
   return total;
@@ -1092,46 +1076,39 @@ __global__ __launch_bounds__(kWG, 4) void k_round(const RoundArgs* __restrict__ 
   // every workgroup checks the whole placement, so all of them agree to stop
   for (int x = 0; x < kMaxXcd; ++x) {
     const int got = (int)__hip_atomic_load(&r.reg[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (got < r.xcd_nw[x]) {
+    int need = 0;
+    for (int i = 0; i < r.xcd_nw[x]; ++i) need += r.xcd_g[x * r.W + i];
+    if (got < need) {
       if (threadIdx.x == 0) __hip_atomic_store(r.err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return;
     }
   }
-  const int nx = (int)__hip_atomic_load(&r.reg[xcc], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const int nw = r.xcd_nw[xcc];
-  if (nw == 0) return;
-  // split the nx workgroups: one per worker, the rest in proportion to chunks
-  const int32_t* wl = r.xcd_workers + (int64_t)xcc * r.W;
-  int64_t ctot = 0;
-  for (int i = 0; i < nw; ++i) ctot += (r.s[wl[i]] + kWG - 1) / kWG;
-  ctot = max(ctot, (int64_t)1);
-  const int64_t R = nx - nw;
-  int64_t given = 0;
-  for (int i = 0; i < nw; ++i) given += R * ((r.s[wl[i]] + kWG - 1) / kWG) / ctot;
-  const int64_t left = R - given;
+  // this XCD's workgroups, in registration order, go to its workers in list
+  // order, r.xcd_g of them each; surplus workgroups leave at once
   int w = -1, rank = 0, nwg = 0;
   {
-    int64_t cum = 0;
-    for (int i = 0; i < nw; ++i) {
-      const int64_t ci = (r.s[wl[i]] + kWG - 1) / kWG;
-      // no more workgroups than chunks; surplus workgroups leave at once
-      const int64_t gi = max((int64_t)1, min(ci, 1 + R * ci / ctot + (i < left ? 1 : 0)));
-      if ((int64_t)slot >= cum && (int64_t)slot < cum + gi) {
-        w = wl[i];
-        rank = (int)(slot - cum);
-        nwg = (int)gi;
+    int cum = 0;
+    for (int i = 0; i < r.xcd_nw[xcc]; ++i) {
+      const int gi = r.xcd_g[xcc * r.W + i];
+      if ((int)slot >= cum && (int)slot < cum + gi) {
+        w = r.xcd_workers[xcc * r.W + i];
+        rank = (int)slot - cum;
+        nwg = gi;
       }
       cum += gi;
     }
   }
-  if (w < 0) return;  // cannot happen: the groups cover all nx slots
+  if (w < 0) return;
   const bool leader = rank == 0;
   const int64_t sj = r.s[w];
   const int64_t nch = (sj + kWG - 1) / kWG;
-  // contiguous chunk ranges in units of PPL chunks (one assignment loop step)
+  // contiguous chunk ranges in units of PPL chunks (one assignment loop
+  // step), the units spread as evenly as possible
   const int64_t units = (nch + PPL - 1) / PPL;
-  const int64_t per = (units + nwg - 1) / nwg * PPL;
-  const int64_t c0 = min(nch, (int64_t)rank * per), c1 = min(nch, c0 + per);
+  const int64_t ubase = units / nwg, urem = units % nwg;
+  const int64_t u0 = rank * ubase + min((int64_t)rank, urem);
+  const int64_t u1 = u0 + ubase + (rank < urem ? 1 : 0);
+  const int64_t c0 = min(nch, u0 * PPL), c1 = min(nch, u1 * PPL);
   const int64_t p0 = c0 * kWG, p1 = min(sj, c1 * kWG);
   unsigned int* bar = &r.bar[w].count;
   unsigned int epoch = 0;
@@ -1224,12 +1201,18 @@ __global__ __launch_bounds__(kWG, 4) void k_round(const RoundArgs* __restrict__ 
       const int b = ig % 3;
       assign_range<NP, PPL, true>(r.as, w, p0, p1, it == 0 ? 1 : 0, smem, true, tf3 + b * mc,
                                   dl3 + (int64_t)b * k * NP, dc3 + b * k);
-      if (leader) {  // clear the buffer of the next iteration (last read two barriers ago)
+      {  // clear the buffers of the next iteration (last read two barriers ago),
+         // each workgroup its share
         const int bn = (b + 1) % 3;
-        for (int e = threadIdx.x; e < k * NP; e += kWG)
-          __hip_atomic_store(dl3 + (int64_t)bn * k * NP + e, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        for (int j = threadIdx.x; j < k; j += kWG)
-          __hip_atomic_store(dc3 + bn * k + j, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int tot_e = k * NP + k;
+        const int share = (tot_e + nwg - 1) / nwg;
+        const int e1 = min(tot_e, (rank + 1) * share);
+        for (int e = rank * share + threadIdx.x; e < e1; e += kWG) {
+          if (e < k * NP)
+            __hip_atomic_store(dl3 + (int64_t)bn * k * NP + e, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          else
+            __hip_atomic_store(dc3 + bn * k + (e - k * NP), 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
       }
       xcd_barrier(bar, nwg, epoch, r.err, false);
       // every arrival's atomics and stores are complete in L2

@@ -1,0 +1,178 @@
+"""GPU parity of the wide-point path (padded dimension above 64: matrix-core
+dot products, separate fixed-point update) against the FP64 oracle, through
+the C ABI.  Same bars as the narrow path:
+
+  * labels identical except the oracle's near ties ((d2 - d1) < 1e-5 d2);
+  * objectives within 1e-6 relative;
+  * one teacher-forced update within 1 ulp of fp32(FP64 mean of the GPU's
+    own labels);
+  * Algorithm 1 end to end within 1% of the oracle's f(C, X), and bitwise
+    identical between the execution modes.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import bigmeans as obm
+from oracle import kmeans as okm
+from paper_2403_18766_amd import datagen
+from tests.gpu_common import require_gpu, say, to_dev, ulp_diff_f32
+
+pytestmark = pytest.mark.gpu
+
+F_TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2403_18766_amd import api as a
+    return a
+
+
+def _check_objective(api, dev, X, C, label):
+    say("objective wide", label, X.shape, C.shape)
+    f, lab, near = api.objective(to_dev(X, dev), to_dev(C, dev))
+    lab = lab.cpu().numpy()
+    olab, od1, od2, onear = okm.assign(X, C, return_second=True)
+    fo = math.fsum(od1.tolist())
+    assert abs(f - fo) <= F_TOL * abs(fo) + 1e-300, (f, fo)
+    ok = ~onear
+    mism = np.nonzero(lab[ok] != olab[ok])[0]
+    assert mism.size == 0, f"{mism.size} label mismatches outside near ties"
+    assert abs(int(near) - int(onear.sum())) <= max(2, int(0.01 * onear.sum()))
+    return f, lab
+
+
+def test_objective_vmf768(dev, api):
+    # unit vectors in 768-D from 100 vMF clusters, k = 100 (one group of 128 centres)
+    X = datagen.make("vmf768", m=20_000)
+    r = np.random.default_rng(0)
+    C = X[r.choice(len(X), 100, replace=False)].copy()
+    _check_objective(api, dev, X, C, "vmf768 k=100")
+
+
+@pytest.mark.parametrize("m,n,k", [(1, 65, 1), (300, 65, 7), (4_099, 101, 33), (2_049, 256, 200),
+                                   (1_000, 768, 129), (513, 1_000, 5)])
+def test_objective_wide_shapes(dev, api, m, n, k):
+    # ragged chunks, n not a multiple of 4 (scalar row reads), k above one
+    # centre group, a single point
+    r = np.random.default_rng(m + n + k)
+    X = r.standard_normal((m, n)).astype(np.float32)
+    C = r.standard_normal((k, n)).astype(np.float32)
+    _check_objective(api, dev, X, C, f"m={m} n={n} k={k}")
+
+
+def test_objective_wide_far_from_origin(dev, api):
+    # large ||x|| and ||c||: most points go through the direct-form re-decision
+    r = np.random.default_rng(1)
+    X = (300.0 + r.standard_normal((3_000, 96))).astype(np.float32)
+    C = (300.0 + r.standard_normal((12, 96))).astype(np.float32)
+    _check_objective(api, dev, X, C, "offset 300")
+
+
+def test_objective_wide_ties(dev, api):
+    r = np.random.default_rng(2)
+    X = r.integers(-3, 4, size=(2_000, 72)).astype(np.float32)
+    C = r.integers(-3, 4, size=(9, 72)).astype(np.float32)
+    C[7] = C[2]
+    f, lab = _check_objective(api, dev, X, C, "duplicate centres")
+    assert not np.any(lab == 7)
+
+
+def test_lloyd_wide_one_update_teacher_forced(dev, api):
+    S = datagen.make("vmf768", m=12_000, seed=1)
+    k = 100
+    r = np.random.default_rng(3)
+    C0 = S[r.choice(len(S), k, replace=False)].copy()
+    say("lloyd wide one update", S.shape, k)
+    res = api.lloyd(to_dev(S, dev), to_dev(C0, dev), max_iter=1, tol=0.0)
+    C1 = res["C"].cpu().numpy()
+    assert res["iters"] == 1
+    lab0, _, _, near0 = okm.assign(S, C0, return_second=True)
+    want, _ = okm.cluster_means(S, lab0, k, C0)
+    touched = np.zeros(k, bool)
+    touched[np.unique(lab0[near0])] = True
+    u = ulp_diff_f32(C1[~touched], want.astype(np.float32)[~touched])
+    assert u.max() <= 1, u.max()
+    # labels returned after an odd number of updates come from the second buffer
+    lab1 = res["labels"].cpu().numpy()
+    olab1, od1, _, onear1 = okm.assign(S, C1, return_second=True)
+    assert np.array_equal(lab1[~onear1], olab1[~onear1])
+    fo = math.fsum(od1.tolist())
+    assert abs(res["f"] - fo) <= F_TOL * fo
+
+
+@pytest.mark.parametrize("s,n,k,seed", [(5_000, 768, 20, 4), (3_001, 130, 150, 5), (700, 66, 3, 6)])
+def test_lloyd_wide_full_run(dev, api, s, n, k, seed):
+    r = np.random.default_rng(seed)
+    centres = r.standard_normal((k, n)) * 4
+    S = (centres[r.integers(0, k, s)] + r.standard_normal((s, n))).astype(np.float32)
+    C0 = S[r.choice(s, k, replace=False)].copy()
+    say("lloyd wide full", S.shape, k)
+    res = api.lloyd(to_dev(S, dev), to_dev(C0, dev), max_iter=300, tol=1e-4)
+    o = okm.lloyd(S, C0, 300, 1e-4)
+    assert abs(res["iters"] - o["iters"]) <= 1
+    if res["iters"] == o["iters"]:
+        assert np.abs(res["C"].cpu().numpy() - o["C"]).max() <= 1e-5 * np.abs(S).max()
+        assert abs(res["f"] - o["f"]) <= 1e-5 * o["f"]
+    fo = okm.objective(S, res["C"].cpu().numpy())
+    assert abs(res["f"] - fo) <= F_TOL * fo
+    lab = res["labels"].cpu().numpy()
+    olab, _, _, onear = okm.assign(S, res["C"].cpu().numpy(), return_second=True)
+    assert np.array_equal(lab[~onear], olab[~onear])
+    deg = res["deg"].cpu().numpy().astype(bool)
+    assert np.array_equal(deg, np.bincount(olab, minlength=k) == 0)
+
+
+def test_lloyd_wide_deterministic(dev, api):
+    S = datagen.make("vmf768", m=8_000, seed=2)
+    C0 = S[:60].copy()
+    a = api.lloyd(to_dev(S, dev), to_dev(C0, dev))
+    b = api.lloyd(to_dev(S, dev), to_dev(C0, dev))
+    assert a["f"] == b["f"] and a["iters"] == b["iters"]
+    assert np.array_equal(a["C"].cpu().numpy(), b["C"].cpu().numpy())
+    assert np.array_equal(a["labels"].cpu().numpy(), b["labels"].cpu().numpy())
+
+
+def test_kmeanspp_wide_valid(dev, api):
+    # every pick is a sample row; the seeded centres' potential is within the
+    # oracle K-means++ range on the same sample (greedy, 3 candidates)
+    S = datagen.make("vmf768", m=4_000, seed=3)
+    k = 20
+    C = np.zeros((k, S.shape[1]), np.float32)
+    deg = np.ones(k, np.uint8)
+    Cg, dg, picks = api.seed(to_dev(S, dev), to_dev(C, dev), to_dev(deg, dev), 3, seed=1,
+                             worker=0, g=0, return_picks=True)
+    picks = picks.cpu().numpy()
+    assert dg.cpu().numpy().sum() == 0
+    assert np.array_equal(Cg.cpu().numpy(), S[picks[:, 0]])
+    assert len(set(picks[:, 0].tolist())) == k
+    Co, _, _ = okm.kmeanspp(S, C, deg.astype(bool), 3, 1, 0, 0)
+    fg = okm.objective(S, Cg.cpu().numpy())
+    fo = okm.objective(S, Co)
+    assert fg <= 1.5 * fo
+
+
+def test_bigmeans_wide_end_to_end_and_modes(dev, api):
+    # 768-D unit vectors, k = 10, 4 workers of 2,000 points, 2 rounds x 3 passes
+    X = datagen.make("vmf768", m=20_000, seed=4)
+    P = dict(k=10, workers=4, rounds_T=2, passes_p=3, s_min=2000, s_max=2000, seed=7,
+             size_policy=1)
+    say("bigmeans wide", X.shape, P)
+    runs = [api.bigmeans_run(to_dev(X, dev), api.RunParams(batched=b, **P)) for b in (1, 2, 0)]
+    o = obm.bigmeans_run(X, obm.Params(**P))
+    g = runs[0]
+    assert abs(g["f_full"] - o["f_full"]) <= 0.01 * o["f_full"]
+    fo = okm.objective(X, g["C_best"].cpu().numpy())
+    assert abs(g["f_full"] - fo) <= F_TOL * fo
+    for b in runs[1:]:
+        assert g["f_full"] == b["f_full"] and g["best_worker"] == b["best_worker"]
+        assert np.array_equal(g["C_best"].cpu().numpy(), b["C_best"].cpu().numpy())
+        assert np.array_equal(g["Y"].cpu().numpy(), b["Y"].cpu().numpy())
