@@ -25,6 +25,22 @@ __device__ inline int wave_sum_i32(int v) {
   return v;
 }
 
+// Value of v in lane l (l uniform), broadcast through SGPRs.
+__device__ inline double lane_value(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const unsigned int lo = (unsigned int)__builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const unsigned int hi = (unsigned int)__builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum of the 64 lane values in lane order, the same in every lane.
+__device__ inline double wave_ordered_sum(double v) {
+  double total = 0.0;
+#pragma unroll 8
+  for (int l = 0; l < 64; ++l) total += lane_value(v, l);
+  return total;
+}
+
 // Deterministic sum of v[0..cnt) by one wave: lane l adds a contiguous chunk
 // in order, then the 64 chunk totals are added in lane order.  The result is
 // the same in every lane and depends only on cnt and the values.
@@ -33,10 +49,17 @@ __device__ inline double wave_chunked_sum(const double* __restrict__ v, int64_t 
   const int64_t cs = (cnt + 63) / 64;
   const int64_t lo = min(cnt, (int64_t)lane * cs), hi = min(cnt, lo + cs);
   double tot = 0.0;
-  for (int64_t q = lo; q < hi; ++q) tot += v[q];
-  double total = 0.0;
-  for (int l = 0; l < 64; ++l) total += __shfl(tot, l, 64);
-  return total;
+  if (cs <= 4) {  // loads issued together, added in the same order
+    double t[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) t[q] = lo + q < hi ? v[lo + q] : 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (lo + q < hi) tot += t[q];
+  } else {
+    for (int64_t q = lo; q < hi; ++q) tot += v[q];
+  }
+  return wave_ordered_sum(tot);
 }
 
 // Fixed-point value of one coordinate: trunc(x * 2^shift_d), exact in int64

@@ -614,11 +614,13 @@ int xcd_layout(bm_ctx* c, int cap) {
 
 // One round of Algorithm 1 for all workers in one cooperative launch.
 //
-// Placement: a worker's Lloyd iteration costs about F + L * (assignment steps
-// of its busiest workgroup), and it runs about `iters[w]` of them (taken from
-// its previous round).  Workers go to XCDs largest predicted work first, each
-// to the XCD with the least work per workgroup; then each XCD hands its spare
-// workgroups one at a time to the worker with the largest predicted time.
+// Placement: a worker's Lloyd iteration costs about F + L * u, u = assignment
+// steps of its busiest workgroup (units of 512 points), and it runs about
+// iters[w] iterations in the round.  Workers go to XCDs largest predicted work
+// (iters x units) first, each to the XCD with the least work per workgroup.
+// On each XCD every worker starts with one workgroup; the spare workgroups
+// then go to the worker with the largest predicted time, each time as many as
+// it needs for one assignment step fewer.
 int round_persistent(bm_ctx* c, const float* X, const bm_params& p, int t,
                      const std::vector<int64_t>& sizes, const std::vector<int32_t>& recalc,
                      const std::vector<double>& iters, RoundResult* res) {
@@ -659,8 +661,9 @@ int round_persistent(bm_ctx* c, const float* X, const bm_params& p, int t,
     xnw[best] += 1;
     load[best] += work[w];
   }
+  auto steps = [&](int w, int64_t g) { return (units[w] + g - 1) / g; };
   auto t_of = [&](int w, int64_t g) {
-    return std::max(1.0, iters[w]) * (kF + kL * (double)((units[w] + g - 1) / g));
+    return std::max(1.0, iters[w]) * (kF + kL * (double)steps(w, g));
   };
   for (int x = 0; x < bm::kMaxXcd; ++x) {
     const int nw = xnw[x];
@@ -668,19 +671,26 @@ int round_persistent(bm_ctx* c, const float* X, const bm_params& p, int t,
     int32_t* g = &xg[(size_t)x * W];
     const int32_t* wl = &xw[(size_t)x * W];
     for (int i = 0; i < nw; ++i) g[i] = 1;
-    for (int spare = c->xcd_wgs[x] - nw; spare > 0; --spare) {
+    for (int64_t spare = c->xcd_wgs[x] - nw; spare > 0;) {
       int bi = -1;
       double bt = 0.0;
+      int64_t bneed = 0;
       for (int i = 0; i < nw; ++i) {
-        if (g[i] >= units[wl[i]]) continue;  // one more workgroup would idle
-        const double tw = t_of(wl[i], g[i]);
+        const int w = wl[i];
+        const int64_t st = steps(w, g[i]);
+        if (st <= 1) continue;
+        const int64_t gn = (units[w] + st - 2) / (st - 1);  // workgroups for one step fewer
+        if (gn - g[i] > spare) continue;
+        const double tw = t_of(w, g[i]);
         if (bi < 0 || tw > bt) {
           bi = i;
           bt = tw;
+          bneed = gn - g[i];
         }
       }
       if (bi < 0) break;
-      g[bi] += 1;
+      g[bi] += (int32_t)bneed;
+      spare -= bneed;
     }
   }
   const int64_t mc = c->max_chunks;
@@ -1184,11 +1194,32 @@ BM_API int bm_bigmeans_run(bm_ctx* c, const float* X, const bm_params* params, f
     // launch (the multi-launch path below runs when it does not fit the device)
     bool round_done = false;
     std::vector<int32_t> rflag(W, 0);
-    if (t == 0) iters_prev.assign(W, 1.0);
+    // Lloyd iterations expected this round: a least-squares line in log2(s)
+    // through the previous round's workers (smaller samples need more
+    // iterations); before any round, more for smaller samples as well.
+    std::vector<double> iters_pred(W, 1.0);
+    {
+      double sx = 0, sy = 0, sxx = 0, sxy = 0;
+      for (int w = 0; w < W && t > 0; ++w) {
+        const double lx = std::log2((double)std::max<int64_t>(1, s_cur[w]));
+        sx += lx;
+        sy += iters_prev[w];
+        sxx += lx * lx;
+        sxy += lx * iters_prev[w];
+      }
+      const double den = W * sxx - sx * sx;
+      for (int w = 0; w < W; ++w) {
+        const double lx = std::log2((double)std::max<int64_t>(1, s_new[w]));
+        double v;
+        if (t == 0 || !(den > 1e-9)) v = t == 0 ? 1.0 + std::max(0.0, 16.0 - lx) : sy / W;
+        else v = (sy - (W * sxy - sx * sy) / den * sx) / W + (W * sxy - sx * sy) / den * lx;
+        iters_pred[w] = std::max(1.0, v);
+      }
+    }
     RoundResult rres;
     if (p.batched == 1 && c->round_ok && cp <= bm::kMaxRegDim) {  // wide points: multi-launch
       for (int w = 0; w < W; ++w) rflag[w] = (std::isfinite(fhat[w]) && s_new[w] != s_cur[w]) ? 1 : 0;
-      const int rc = round_persistent(c, X, p, t, s_new, rflag, iters_prev, &rres);
+      const int rc = round_persistent(c, X, p, t, s_new, rflag, iters_pred, &rres);
       if (rc == kRoundNoFit) c->round_ok = false;
       else BM_TRY(rc);
       round_done = rc == BM_OK;

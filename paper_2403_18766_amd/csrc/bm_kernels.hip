@@ -684,10 +684,11 @@ __device__ inline int other_slot(int dcur, int c) { return c < dcur ? c : c + 1;
 // been written by another workgroup before the last barrier).
 __device__ inline KppState load_ks(const KppState* p) {
   KppState ks;
-  const volatile unsigned long long* pd = reinterpret_cast<const volatile unsigned long long*>(p);
+  const unsigned long long* pd = reinterpret_cast<const unsigned long long*>(p);
   unsigned long long* qd = reinterpret_cast<unsigned long long*>(&ks);
 #pragma unroll
-  for (int i = 0; i < (int)(sizeof(KppState) / 8); ++i) qd[i] = pd[i];
+  for (int i = 0; i < (int)(sizeof(KppState) / 8); ++i)
+    qd[i] = __hip_atomic_load(pd + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return ks;
 }
 
@@ -754,11 +755,25 @@ __device__ inline double wave_prefix_search(const T* v, int64_t cnt, double tau,
   const int lane = threadIdx.x & 63;
   const int64_t cs = (cnt + 63) / 64;
   const int64_t lo = min(cnt, (int64_t)lane * cs), hi = min(cnt, lo + cs);
+  // up to 4 values per lane are loaded together and kept for the search
+  T pre[4];
+  const bool few = cs <= 4;
+  if (few) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) pre[q] = lo + q < hi ? v[lo + q] : (T)0;
+  }
   double tot = 0.0;
-  for (int64_t q = lo; q < hi; ++q) tot += (double)v[q];
+  if (few) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (lo + q < hi) tot += (double)pre[q];
+  } else {
+    for (int64_t q = lo; q < hi; ++q) tot += (double)v[q];
+  }
   double carry = 0.0, total = 0.0;
+#pragma unroll 8
   for (int l = 0; l < 64; ++l) {
-    const double tl = __shfl(tot, l, 64);
+    const double tl = lane_value(tot, l);
     if (l == lane) carry = total;
     total += tl;
   }
@@ -766,13 +781,27 @@ __device__ inline double wave_prefix_search(const T* v, int64_t cnt, double tau,
     int64_t found = -1;
     double bef = 0.0;
     double r = carry;
-    for (int64_t q = lo; q < hi; ++q) {
-      const double prev = r;
-      r += (double)v[q];
-      if (r > tau) {
-        found = q;
-        bef = prev;
-        break;
+    if (few) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (found < 0 && lo + q < hi) {
+          const double prev = r;
+          r += (double)pre[q];
+          if (r > tau) {
+            found = lo + q;
+            bef = prev;
+          }
+        }
+      }
+    } else {
+      for (int64_t q = lo; q < hi; ++q) {
+        const double prev = r;
+        r += (double)v[q];
+        if (r > tau) {
+          found = q;
+          bef = prev;
+          break;
+        }
       }
     }
     // smallest lane that found a crossing
@@ -1019,9 +1048,7 @@ __device__ inline double wave_chunked_sum_dev(const double* v, int64_t cnt) {
   } else {
     for (int64_t q = lo; q < hi; ++q) tot += load_dev(v + q);
   }
-  double total = 0.0;
-  for (int l = 0; l < 64; ++l) total += __shfl(tot, l, 64);
-  return total;
+  return wave_ordered_sum(tot);
 }
 
 __device__ inline void sample_range(const RoundArgs& r, int w, uint32_t purpose, uint64_t g,
@@ -1040,6 +1067,126 @@ __device__ inline void lds_norms(const float* sC, float* sCn, int k) {
     double q = 0.0;
     for (int d = 0; d < NP; ++d) q += (double)sC[j * NP + d] * (double)sC[j * NP + d];
     sCn[j] = (float)q;
+  }
+}
+
+// Direct-form distance of a register-resident point, with the operation
+// order of dist_direct_mem over the first n dimensions (partial sum d mod 4
+// for the first floor(n/4)*4 dimensions, the rest into the first partial).
+template <int NP>
+__device__ inline float dist_direct_regn(const float (&x)[NP], const float* __restrict__ c, int n) {
+  float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
+  const int n4 = n & ~3;
+#pragma unroll
+  for (int d = 0; d < NP; d += 4) {
+    if (d < n4) {
+      const float t0 = x[d] - c[d], t1 = x[d + 1] - c[d + 1];
+      const float t2 = x[d + 2] - c[d + 2], t3 = x[d + 3] - c[d + 3];
+      p0 = fmaf(t0, t0, p0);
+      p1 = fmaf(t1, t1, p1);
+      p2 = fmaf(t2, t2, p2);
+      p3 = fmaf(t3, t3, p3);
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < NP; ++d) {
+    if (d >= n4 && d < n) {
+      const float t = x[d] - c[d];
+      p0 = fmaf(t, t, p0);
+    }
+  }
+  return (p0 + p1) + (p2 + p3);
+}
+
+// The rows [i0, i0 + 256) of a worker's padded sample, one per thread.
+template <int NP>
+__device__ inline void load_row(const float* S, int64_t i, bool valid, float (&x)[NP]) {
+  if (valid) {
+    const float4* src = reinterpret_cast<const float4*>(S + i * (int64_t)NP);
+#pragma unroll
+    for (int q = 0; q < NP / 4; ++q) {
+      const float4 v = src[q];
+      x[4 * q] = v.x;
+      x[4 * q + 1] = v.y;
+      x[4 * q + 2] = v.z;
+      x[4 * q + 3] = v.w;
+    }
+  } else {
+#pragma unroll
+    for (int d = 0; d < NP; ++d) x[d] = 0.f;
+  }
+}
+
+// K-means++ in the persistent kernel: the same values as kpp_init_tile and
+// kpp_pot_tile for the tiles [c0, c1) of one worker, with the workgroup's
+// points in registers, the centres (the incumbent in LDS) or the candidate
+// rows (staged in LDS) as broadcasts, and one synchronisation per tile.
+template <int NP>
+__device__ void kpp_init_range(const KppArgs& a, int job, int64_t c0, int64_t c1,
+                               const float* sI, const uint8_t* sIdeg, double* red) {
+  const KppState ks = load_ks(a.ks + job);
+  if (ks.ntodo == 0 || !ks.has_d) return;
+  const int64_t s = a.s[job];
+  const float* S = a.S + job * a.S_stride;
+  const int k = a.k, n = a.n, wv = threadIdx.x >> 6;
+  for (int64_t tile = c0; tile < c1; ++tile) {
+    if (tile * kDTile >= s) break;
+    const int64_t i = tile * kDTile + threadIdx.x;
+    const bool valid = i < s;
+    float x[NP];
+    load_row<NP>(S, i, valid, x);
+    float dmin = __builtin_inff();
+    if (valid) {
+      for (int j = 0; j < k; ++j)
+        if (!sIdeg[j]) dmin = min_nan(dmin, dist_direct_regn<NP>(x, sI + j * NP, n));
+      a.D[0 * a.D_slot_stride + job * a.D_job_stride + i] = dmin;
+    }
+    const double part = wave_sum_f64(valid ? (double)dmin : 0.0);
+    if ((threadIdx.x & 63) == 0) red[wv] = part;
+    __syncthreads();
+    if (threadIdx.x == 0)
+      a.Dt[(0 * (int64_t)a.njobs + job) * a.ndt_max + tile] = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();
+  }
+}
+
+template <int NP>
+__device__ void kpp_pot_range(const KppArgs& a, int job, int64_t c0, int64_t c1, float* rows,
+                              double* red) {
+  const KppState ks = load_ks(a.ks + job);
+  if (ks.ncand == 0) return;
+  const int64_t s = a.s[job];
+  const float* S = a.S + job * a.S_stride;
+  const int n = a.n, wv = threadIdx.x >> 6;
+  for (int e = threadIdx.x; e < ks.ncand * NP; e += kWG) {
+    const int c = e / NP, d = e - c * NP;
+    rows[e] = S[(int64_t)ks.cand[c] * NP + d];
+  }
+  __syncthreads();
+  for (int64_t tile = c0; tile < c1; ++tile) {
+    if (tile * kDTile >= s) break;
+    const int64_t i = tile * kDTile + threadIdx.x;
+    const bool valid = i < s;
+    float x[NP];
+    load_row<NP>(S, i, valid, x);
+    float dcur = 0.f;
+    if (valid && ks.has_d) dcur = a.D[(int64_t)ks.dcur * a.D_slot_stride + job * a.D_job_stride + i];
+    for (int c = 0; c < ks.ncand; ++c) {
+      float m = 0.f;
+      if (valid) {
+        const float dc = dist_direct_regn<NP>(x, rows + c * NP, n);
+        m = ks.has_d ? min_nan(dcur, dc) : dc;
+        a.D[(int64_t)other_slot(ks.dcur, c) * a.D_slot_stride + job * a.D_job_stride + i] = m;
+      }
+      const double part = wave_sum_f64(valid ? (double)m : 0.0);
+      if ((threadIdx.x & 63) == 0) red[c * 4 + wv] = part;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int c = 0; c < ks.ncand; ++c)
+        a.Dt[((int64_t)other_slot(ks.dcur, c) * a.njobs + job) * a.ndt_max + tile] =
+            (red[c * 4] + red[c * 4 + 1]) + (red[c * 4 + 2] + red[c * 4 + 3]);
+    __syncthreads();
   }
 }
 
@@ -1064,6 +1211,8 @@ __global__ __launch_bounds__(kWG, 4) void k_round(const RoundArgs* __restrict__ 
   uint8_t* sIdeg = reinterpret_cast<uint8_t*>(sI + k * NP);
   __shared__ unsigned int sh_slot;
   __shared__ double sh_f;
+  __shared__ float krows[3 * NP];  // K-means++ candidate rows
+  __shared__ double kred[12];      // K-means++ per-wave partial sums
 
   // ---- registration on this workgroup's XCD, one device-wide barrier ----
   unsigned int xcc;
@@ -1174,12 +1323,12 @@ __global__ __launch_bounds__(kWG, 4) void k_round(const RoundArgs* __restrict__ 
         kpp_setup_job(ka, w);
       }
       xcd_barrier(bar, nwg, epoch, r.err);
-      for (int64_t tl = c0; tl < c1; ++tl) kpp_init_tile(ka, w, tl);
+      kpp_init_range<NP>(ka, w, c0, c1, sI, sIdeg, kred);
       xcd_barrier(bar, nwg, epoch, r.err);
       for (int step = 0; step < ntodo; ++step) {
         if (leader && threadIdx.x < 64) kpp_step_job(ka, w);
         xcd_barrier(bar, nwg, epoch, r.err);
-        for (int64_t tl = c0; tl < c1; ++tl) kpp_pot_tile(ka, w, tl);
+        kpp_pot_range<NP>(ka, w, c0, c1, krows, kred);
         xcd_barrier(bar, nwg, epoch, r.err);
       }
       if (leader && threadIdx.x < 64) kpp_step_job(ka, w);  // commits the last step
