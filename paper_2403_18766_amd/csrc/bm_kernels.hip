@@ -991,7 +991,9 @@ __device__ inline void drain_vm() { asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)"
 
 // Barrier of one worker's workgroups, all on one XCD.  The arrival counter
 // only grows: the e-th barrier of a launch waits until it reaches e * nwg
-// (the host zeroes it before the launch).  Arrival is a non-returning L2
+// (the host zeroes it before the launch).  A wait ends after two seconds and
+// sets the error flag; once the flag is set no wait lasts longer than 64 polls,
+// so a launch always ends.  Arrival is a non-returning L2
 // atomic issued after this workgroup's stores have completed; the wait polls
 // the counter in L2.  With inv, every wave then invalidates at device scope,
 // so no later load is served from a line its CU's L1 kept from before
@@ -1003,14 +1005,18 @@ __device__ inline void xcd_barrier(unsigned int* count, unsigned int nwg, unsign
   drain_vm();
   __syncthreads();
   epoch += 1;
-  if (threadIdx.x == 0 && nwg > 1 &&
-      __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+  if (threadIdx.x == 0 && nwg > 1) {
     __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const unsigned int target = epoch * nwg;
     const uint64_t t0 = wall_clock64();
-    while ((int)(__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
+    // every 64 polls: give up after the time limit, or at once when an
+    // earlier barrier already timed out (the flag is set)
+    for (unsigned int polls = 1;
+         (int)(__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0;
+         ++polls) {
       __builtin_amdgcn_s_sleep(1);
-      if (timed_out(t0)) {
+      if ((polls & 63) == 0 &&
+          (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || timed_out(t0))) {
         __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         break;
       }
@@ -1198,7 +1204,11 @@ size_t __host__ __device__ inline round_assign_bytes(int cp, int k) {
 template <int NP>
 __global__ __launch_bounds__(kWG, 4) void k_round(const RoundArgs* __restrict__ rp) {
   constexpr int PPL = NP <= 32 ? 2 : 1;
-  const RoundArgs& r = *rp;
+  // the arguments, read many times by every phase, live in LDS
+  __shared__ RoundArgs r_lds;
+  if (threadIdx.x == 0) r_lds = *rp;
+  __syncthreads();
+  const RoundArgs& r = r_lds;
   extern __shared__ __align__(16) unsigned char smem[];
   const int k = r.k, n = r.n;
   // LDS: [assign region: centroids sC, norms sCn, delta sums, counts]
