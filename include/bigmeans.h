@@ -29,6 +29,12 @@
  *     describes the last error of that context.  No call aborts and no C++
  *     exception crosses this interface.
  *   - A context is used by one host thread at a time.
+ *   - Sizes: 1 <= n <= 4096.  Points whose dimension rounded up to 4 is at
+ *     most 64 are assigned with the point in registers and the centroids in
+ *     LDS; wider points with FP32 matrix-core dot products.  k is limited by
+ *     the LDS of one compute unit holding the fixed-point cluster sums
+ *     (about 12 k * n + 8 k bytes <= 160 KiB for narrow points, k <= 310
+ *     for wide ones); larger k returns BM_E_ARG.
  *
  * Randomness (the paper fixes none).  Every random draw comes from the
  * Philox4x64-10 block function B(ctr, key) of Salmon et al. (SC'11) with
@@ -184,7 +190,9 @@ typedef struct bm_params {
   int32_t size_policy; /* bm_size_policy */
   int32_t prec;        /* BM_FP32 */
   int32_t batched;     /* 1: one persistent cooperative launch per round, each worker on
-                             its own group of workgroups (default);
+                             its own group of workgroups inside one XCD (default; wide
+                             points, or a device placement that cannot hold every
+                             worker, run as 2);
                           2: all workers' passes together, one launch per Lloyd step;
                           0: one worker's sample per launch (reference plain path).
                           All three give bitwise identical results. */
