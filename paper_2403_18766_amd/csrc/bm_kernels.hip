@@ -680,17 +680,10 @@ __global__ __launch_bounds__(kWG) void k_copy_incumbent(const float* __restrict_
 // ---------------------------------------------------------------------------
 __device__ inline int other_slot(int dcur, int c) { return c < dcur ? c : c + 1; }
 
-// A job's K-means++ state, read through the vector memory path (it may have
-// been written by another workgroup before the last barrier).
-__device__ inline KppState load_ks(const KppState* p) {
-  KppState ks;
-  const unsigned long long* pd = reinterpret_cast<const unsigned long long*>(p);
-  unsigned long long* qd = reinterpret_cast<unsigned long long*>(&ks);
-#pragma unroll
-  for (int i = 0; i < (int)(sizeof(KppState) / 8); ++i)
-    qd[i] = __hip_atomic_load(pd + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return ks;
-}
+// A job's K-means++ state.  Callers read it after a kernel boundary or after
+// a barrier that invalidated L1; global loads are never scalarised in this
+// library (build flag), so the scalar cache cannot hold a stale copy.
+__device__ inline KppState load_ks(const KppState* p) { return *p; }
 
 
 __device__ __noinline__ void kpp_setup_job(const KppArgs& a, int job) {
