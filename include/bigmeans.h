@@ -11,7 +11,8 @@
  *   - Lloyd K-means iterations on a sample (Algorithm 1; Section 5: at most
  *     300 iterations, relative tolerance 1e-4);
  *   - the MSSC objective f(C, X) of Eq. (1) with nearest-centre labels;
- *   - Algorithm 1 end to end (bm_bigmeans_run).
+ *   - Algorithm 1 end to end (bm_bigmeans_run);
+ *   - a serving loop of single-pass jobs of competing workers (bm_serve).
  *
  * Conventions for every call
  *   - Point, sample, centroid, label, index and flag arrays are DEVICE
@@ -232,6 +233,80 @@ typedef void (*bm_trace_cb)(void* user, int32_t round, const float* C_all_dev,
 BM_API int bm_bigmeans_run(bm_ctx* ctx, const float* X, const bm_params* params,
                            float* C_best_out, int32_t* Y_out, bm_result* out,
                            bm_trace_cb cb, void* user);
+
+/* ---- Serving: sample-solve jobs of competing workers, continuously batched ----
+ *
+ * One job is one pass of Algorithm 1 for one competing worker: a fresh sample
+ * of size s (re-evaluating the worker's incumbent first when s differs from
+ * its previous job's size), K-means++ for the incumbent's degenerate
+ * centroids, Lloyd, and strict-improvement acceptance.  Jobs of one
+ * (dataset, k, worker) share that worker's incumbent, which stays on the
+ * device for the whole call, and run one after another in arrival order;
+ * all other jobs are independent.  Jobs join the running set as soon as they
+ * have arrived, their worker is idle, a workspace slot of their (dataset, k)
+ * is free and the in-flight bytes stay within the budget; every Lloyd
+ * iteration advances all running jobs together, and a finished job leaves
+ * at once.  Each job's result is bitwise the same alone and in any mix.
+ *
+ * Randomness: the job's worker key is w' = (dataset << 20) | (k << 10) | worker
+ * (dataset < 16, k < 1024, worker < 1024) in the key convention above; the
+ * g-th job of a worker (g = 0, 1, ...) samples with purpose SAMPLE and
+ * counter g, seeds with K-means++ counter g, and re-evaluates with purpose
+ * RECALC and counter g. */
+typedef struct bm_dataset {
+  const float* X;  /* device, m x n FP32 rows, resident for the call */
+  int64_t m;
+  int32_t n;
+  int32_t pad_;
+} bm_dataset;
+
+typedef struct bm_job {
+  double arrival;  /* seconds after the start of bm_serve (0 for all: no pacing) */
+  int64_t s;       /* sample size, 1 <= k <= s <= m */
+  int32_t dataset; /* index into the dataset array */
+  int32_t k;
+  int32_t worker;
+  int32_t prec;    /* BM_FP32 */
+} bm_job;
+
+typedef struct bm_job_result {
+  double f;            /* objective of the job's Lloyd result on its sample */
+  double f_incumbent;  /* the worker's incumbent objective after the job */
+  double admitted;     /* seconds after the start: joined the running set */
+  double finished;     /* seconds after the start: result final */
+  int32_t iters;       /* Lloyd centroid updates */
+  int32_t accepted;    /* the result replaced the incumbent */
+  int32_t ndeg;        /* empty clusters of the result */
+  int32_t pad_;
+} bm_job_result;
+
+typedef struct bm_serve_params {
+  uint64_t seed;
+  int64_t budget_bytes; /* device memory for job workspaces (samples, labels, sums) */
+  int32_t max_slots;    /* running jobs per (dataset, k) at most */
+  int32_t max_iter;     /* Lloyd update cap (Section 5: 300) */
+  int32_t n_candidates; /* K-means++ candidates (Section 5: 3) */
+  int32_t paced;        /* 1: a job cannot start before its arrival time (wall clock) */
+  double tol;           /* Lloyd relative tolerance (Section 5: 1e-4) */
+} bm_serve_params;
+
+typedef struct bm_serve_stats {
+  double seconds;        /* wall time of the call */
+  int64_t steps;         /* Lloyd iterations of the running set */
+  int64_t peak_running;  /* most jobs running together */
+  int64_t peak_bytes;    /* most in-flight workspace bytes */
+  int64_t slot_bytes;    /* workspace reserved for all slots */
+} bm_serve_stats;
+
+/* Run the job list (any order of arrival times) to completion.
+ *   datasets  host array of nds datasets (device rows).
+ *   jobs      host array of njobs jobs.   results  host, njobs entries.
+ *   stats     host (may be NULL).
+ * Returns BM_E_ARG for invalid jobs or a budget too small for any slot.
+ * Synchronises the stream. */
+BM_API int bm_serve(bm_ctx* ctx, const bm_dataset* datasets, int32_t nds, const bm_job* jobs,
+                    int32_t njobs, const bm_serve_params* params, bm_job_result* results,
+                    bm_serve_stats* stats);
 
 /* Kernel timing of the Lloyd assignment (the dominant kernel), for
  * measurement.  With profiling on, every assignment launch of a Lloyd

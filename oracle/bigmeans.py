@@ -108,6 +108,30 @@ def _sample(X, s, seed, worker, purpose, g):
     return X[idx]
 
 
+def worker_pass(X, C, deg, fhat, s_prev, s, seed, worker, g, g_recalc, n_candidates=3,
+                max_iter=300, tol=1e-4):
+    """One pass of one worker of Algorithm 1 (the body of its inner loop).
+
+    If the worker already has an incumbent (f_hat finite) and its sample size
+    changed (s != s_prev), f_hat is first re-evaluated on a fresh sample of
+    size s (purpose RECALC, counter g_recalc; Section 4.2).  Then a new sample
+    S (purpose SAMPLE, counter g), greedy K-means++ for the degenerate
+    centroids on S, K-means from the result, and acceptance only on a strict
+    improvement of f_hat.  Returns a dict with the new incumbent (C, deg,
+    fhat), the pass's Lloyd objective f and updates iters, and accepted."""
+    if fhat < math.inf and s != s_prev:
+        S_re = _sample(X, s, seed, worker, rng.PURPOSE_RECALC, g_recalc)
+        fhat = kmeans.objective(S_re, C)
+    S = _sample(X, s, seed, worker, rng.PURPOSE_SAMPLE, g)
+    C0, _, _ = kmeans.kmeanspp(S, C, deg, n_candidates, seed, worker, g)
+    res = kmeans.lloyd(S, C0, max_iter, tol)
+    accepted = res["f"] < fhat
+    if accepted:
+        C, deg, fhat = res["C"], res["deg"], res["f"]
+    return {"C": C, "deg": deg, "fhat": fhat, "f": res["f"], "iters": res["iters"],
+            "accepted": accepted}
+
+
 def bigmeans_run(X, params, keep_trace=False):
     """Run Algorithm 1 on X (m x n).  Returns a dict with C_best, Y, s_opt,
     f_full, the winning worker, the list L and per-round statistics."""
@@ -131,20 +155,16 @@ def bigmeans_run(X, params, keep_trace=False):
         round_passes = [0] * N_BINS
         for w in range(W):
             s_new, b = draw_size(P, w, t, bin_stats)
-            if fhat[w] < math.inf and s_new != s_cur[w]:
-                S_re = _sample(X, s_new, P.seed, w, rng.PURPOSE_RECALC, t)
-                fhat[w] = kmeans.objective(S_re, C[w])
-            s_cur[w] = s_new
             for q in range(P.passes_p):
-                g = t * P.passes_p + q
-                S = _sample(X, s_new, P.seed, w, rng.PURPOSE_SAMPLE, g)
-                C0, _, _ = kmeans.kmeanspp(S, C[w], deg[w], P.n_candidates, P.seed, w, g)
-                res = kmeans.lloyd(S, C0, P.max_iter, P.tol)
+                # the re-evaluation after a size change happens before the first pass
+                res = worker_pass(X, C[w], deg[w], fhat[w], s_cur[w], s_new, P.seed, w,
+                                  t * P.passes_p + q, t, P.n_candidates, P.max_iter, P.tol)
+                s_cur[w] = s_new
+                C[w], deg[w], fhat[w] = res["C"], res["deg"], res["fhat"]
                 lloyd_iters += res["iters"] + 1
                 lloyd_dists += (res["iters"] + 1) * s_new * k
                 round_passes[b] += 1
-                if res["f"] < fhat[w]:
-                    C[w], deg[w], fhat[w] = res["C"], res["deg"], res["f"]
+                if res["accepted"]:
                     L.append((t, w, q, s_new, b))
                     round_acc[b] += 1
         for i in range(N_BINS):

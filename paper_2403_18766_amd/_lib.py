@@ -41,6 +41,32 @@ class Stats(ct.Structure):
                 ("assign_seconds", ct.c_double), ("finalize_seconds", ct.c_double)]
 
 
+class Dataset(ct.Structure):
+    _fields_ = [("X", ct.c_void_p), ("m", ct.c_int64), ("n", ct.c_int32), ("pad_", ct.c_int32)]
+
+
+class Job(ct.Structure):
+    _fields_ = [("arrival", ct.c_double), ("s", ct.c_int64), ("dataset", ct.c_int32),
+                ("k", ct.c_int32), ("worker", ct.c_int32), ("prec", ct.c_int32)]
+
+
+class JobResult(ct.Structure):
+    _fields_ = [("f", ct.c_double), ("f_incumbent", ct.c_double), ("admitted", ct.c_double),
+                ("finished", ct.c_double), ("iters", ct.c_int32), ("accepted", ct.c_int32),
+                ("ndeg", ct.c_int32), ("pad_", ct.c_int32)]
+
+
+class ServeParams(ct.Structure):
+    _fields_ = [("seed", ct.c_uint64), ("budget_bytes", ct.c_int64), ("max_slots", ct.c_int32),
+                ("max_iter", ct.c_int32), ("n_candidates", ct.c_int32), ("paced", ct.c_int32),
+                ("tol", ct.c_double)]
+
+
+class ServeStats(ct.Structure):
+    _fields_ = [("seconds", ct.c_double), ("steps", ct.c_int64), ("peak_running", ct.c_int64),
+                ("peak_bytes", ct.c_int64), ("slot_bytes", ct.c_int64)]
+
+
 TRACE_CB = ct.CFUNCTYPE(None, ct.c_void_p, ct.c_int32, ct.c_void_p,
                         ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64), ct.c_double)
 
@@ -69,6 +95,9 @@ SIGNATURES = [
     ("bm_draw_size", ct.c_int, [ct.POINTER(Params), ct.c_uint32, ct.c_int32,
                                 ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int64),
                                 ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int32)]),
+    ("bm_serve", ct.c_int, [ct.c_void_p, ct.POINTER(Dataset), ct.c_int32, ct.POINTER(Job),
+                            ct.c_int32, ct.POINTER(ServeParams), ct.POINTER(JobResult),
+                            ct.POINTER(ServeStats)]),
     ("bm_set_profiling", ct.c_int, [ct.c_void_p, ct.c_int]),
     ("bm_get_stats", ct.c_int, [ct.c_void_p, ct.POINTER(Stats)]),
     ("bm_philox4x64", None, [ct.POINTER(ct.c_uint64), ct.POINTER(ct.c_uint64),

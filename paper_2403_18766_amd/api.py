@@ -255,3 +255,44 @@ def philox4x64(ctr, key):
 def paper_size_range(s, m):
     """Section 5: s_min = 0.5 s (rounded up), s_max = min(2 s, m)."""
     return (int(s) + 1) // 2, min(2 * int(s), int(m))
+
+
+def serve(datasets, jobs, seed=0, budget_bytes=200 << 30, max_slots=64, max_iter=300, tol=1e-4,
+          n_candidates=3, paced=False):
+    """bm_serve: run single-pass jobs of competing workers with continuous
+    batching.  `datasets` are device tensors (m x n float32); `jobs` is a list
+    of dicts with keys arrival (s), s, dataset, k, worker.  Returns (results,
+    stats): one dict per job (f, f_incumbent, admitted, finished, iters,
+    accepted, ndeg) and the call's statistics."""
+    if not datasets:
+        raise ValueError("need at least one dataset")
+    dev = datasets[0].device
+    lib, c = _ctx(dev)
+    ds = (_lib.Dataset * len(datasets))()
+    for i, X in enumerate(datasets):
+        X = _dev(X, torch.float32, "X", 2)
+        ds[i].X = X.data_ptr()
+        ds[i].m = X.shape[0]
+        ds[i].n = X.shape[1]
+    nj = len(jobs)
+    jb = (_lib.Job * max(1, nj))()
+    for i, j in enumerate(jobs):
+        jb[i].arrival = float(j.get("arrival", 0.0))
+        jb[i].s = int(j["s"])
+        jb[i].dataset = int(j["dataset"])
+        jb[i].k = int(j["k"])
+        jb[i].worker = int(j["worker"])
+        jb[i].prec = BM_FP32
+    sp = _lib.ServeParams(seed=seed, budget_bytes=int(budget_bytes), max_slots=max_slots,
+                          max_iter=max_iter, n_candidates=n_candidates, paced=1 if paced else 0,
+                          tol=tol)
+    res = (_lib.JobResult * max(1, nj))()
+    st = _lib.ServeStats()
+    rc = lib.bm_serve(c, ds, len(datasets), jb, nj, ct.byref(sp), res, ct.byref(st))
+    _check(lib, c, rc)
+    out = [{"f": r.f, "f_incumbent": r.f_incumbent, "admitted": r.admitted,
+            "finished": r.finished, "iters": r.iters, "accepted": bool(r.accepted),
+            "ndeg": r.ndeg} for r in res[:nj]]
+    stats = {"seconds": st.seconds, "steps": st.steps, "peak_running": st.peak_running,
+             "peak_bytes": st.peak_bytes, "slot_bytes": st.slot_bytes}
+    return out, stats

@@ -10,14 +10,19 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
 #include <limits>
+#include <map>
 #include <new>
 #include <string>
+#include <thread>
+#include <tuple>
 #include <vector>
 
 #include "../../include/bigmeans.h"
@@ -315,35 +320,39 @@ struct BatchView {
   std::vector<int64_t> sizes;
 };
 
-// Run Lloyd on every job of the batch from the centroids in Cp (slots
-// first..first+njobs-1).  Leaves the final centroids in Cp, the job states in
-// js, degenerate flags in deg_work and the final labels in `labels` (or in
-// the workspace label buffer when labels is null).
-int lloyd_batch(bm_ctx* c, const BatchView& b, int max_iter, double tol, int32_t* labels,
-                int64_t lab_stride, bool accept = false, std::vector<JobState>* out = nullptr) {
+// Kernel arguments of Lloyd iterations over the jobs (slots) of a batch.
+struct LloydSetup {
+  bm::AssignArgs a{};
+  bm::FinalizeArgs f{};
+  bool wide = false;
+  int32_t* lab[2] = {nullptr, nullptr};  // wide points: assignment q writes lab[q % 2]
+  int64_t lab_stride = 0;
+  JobState* js = nullptr;
+  unsigned long long* acc = nullptr;
+  int32_t* cnt = nullptr;
+};
+
+// Arguments for the slots first..first+J-1 (tile map set separately).  With
+// `accept`, a stopping job replaces the slot's incumbent on strict improvement.
+int lloyd_setup(bm_ctx* c, const BatchView& b, int max_iter, double tol, int32_t* labels,
+                int64_t lab_stride, bool accept, LloydSetup* L) {
   const int J = b.njobs, first = b.first, k = b.k, cp = b.cp;
   if (!labels) {
     labels = P<int32_t>(c->labels) + (int64_t)first * c->max_s;
     lab_stride = c->max_s;
   }
-  const int tile_pts = choose_tile_pts(b.sizes);
-  TileMap tm = make_tiles(b.sizes, tile_pts);
-  BM_TRY(upload_tiles(c, tm));
-  BM_TRY(upload(c, P<int64_t>(c->sizes) + first, b.sizes.data(), J * sizeof(int64_t)));
-  JobState* js = P<JobState>(c->js) + first;
-  unsigned long long* acc = P<unsigned long long>(c->acc) + (int64_t)first * k * cp;
-  int32_t* cnt = P<int32_t>(c->cnt) + (int64_t)first * k;
-  HIP_TRY(c, bm::launch_job_init(c->stream, js, P<int64_t>(c->sizes) + first, J, k, cp, acc, cnt,
-                                 P<float>(c->Cp) + (int64_t)first * k * cp,
-                                 P<float>(c->cn) + (int64_t)first * k));
-  bm::AssignArgs a{};
+  L->js = P<JobState>(c->js) + first;
+  L->acc = P<unsigned long long>(c->acc) + (int64_t)first * k * cp;
+  L->cnt = P<int32_t>(c->cnt) + (int64_t)first * k;
+  bm::AssignArgs& a = L->a;
+  a = bm::AssignArgs{};
   a.S = b.S;
   a.S_stride = b.S_stride;
   a.ld = b.ld;
   a.n = b.n;
   a.cp = cp;
   a.k = k;
-  a.tile_pts = tile_pts;
+  a.tile_pts = bm::kWG;
   a.max_chunks = (int32_t)c->max_chunks;
   a.vec = (b.ld == cp && aligned16(b.S) && (b.S_stride % 4) == 0) ? 1 : 0;
   a.s = P<int64_t>(c->sizes) + first;
@@ -357,25 +366,26 @@ int lloyd_batch(bm_ctx* c, const BatchView& b, int max_iter, double tol, int32_t
   a.lab_stride = lab_stride;
   a.tf = P<double>(c->tf) + (int64_t)first * c->max_chunks;
   a.tnear = nullptr;
-  a.acc = acc;
-  a.cnt = cnt;
+  a.acc = L->acc;
+  a.cnt = L->cnt;
   a.scale = P<double>(c->scale);
-  a.st = js;
+  a.st = L->js;
 
-  bm::FinalizeArgs f{};
+  bm::FinalizeArgs& f = L->f;
+  f = bm::FinalizeArgs{};
   f.n = b.n;
   f.cp = cp;
   f.k = k;
   f.max_chunks = (int32_t)c->max_chunks;
   f.max_iter = max_iter;
   f.tol = tol;
-  f.acc = acc;
-  f.cnt = cnt;
+  f.acc = L->acc;
+  f.cnt = L->cnt;
   f.tf = a.tf;
   f.inv_scale = P<double>(c->inv_scale);
   f.Cp = P<float>(c->Cp) + (int64_t)first * k * cp;
   f.cn = P<float>(c->cn) + (int64_t)first * k;
-  f.st = js;
+  f.st = L->js;
   f.deg = P<uint8_t>(c->deg_work) + (int64_t)first * k;
   if (accept) {
     f.Cinc = P<float>(c->Cinc) + (int64_t)first * k * b.n;
@@ -383,22 +393,68 @@ int lloyd_batch(bm_ctx* c, const BatchView& b, int max_iter, double tol, int32_t
     f.fhat = P<double>(c->fhat) + first;
   }
 
-  // Wide points: assignment q writes its labels to L[q % 2] (L[0] = labels,
-  // L[1] = a second buffer with the same layout) and a separate kernel adds
-  // the label changes L[(q+1) % 2] -> L[q % 2] to the fixed-point sums.
-  const bool wide = cp > bm::kMaxRegDim;
-  int32_t* lab2 = nullptr;
-  if (wide) {
+  // Wide points: assignment q of a job (q = its iteration count) writes its
+  // labels to lab[q % 2] (lab[0] = labels, lab[1] = a second buffer with the
+  // same layout); a separate kernel adds the label changes to the sums.
+  L->wide = cp > bm::kMaxRegDim;
+  L->lab[0] = labels;
+  L->lab[1] = nullptr;
+  L->lab_stride = lab_stride;
+  if (L->wide) {
     if (J > 1 && lab_stride != c->max_s) return c->fail(BM_E_STATE, "label layout");
-    const size_t need = (size_t)(J - 1) * lab_stride + (size_t)c->max_s;
+    const size_t need = (size_t)c->max_jobs * c->max_s;
     if (c->labels2.bytes < need * sizeof(int32_t)) {
       HIP_TRY(c, hipStreamSynchronize(c->stream));
-      BM_TRY(dev_alloc(c, c->labels2, (size_t)c->max_jobs * c->max_s * sizeof(int32_t)));
+      BM_TRY(dev_alloc(c, c->labels2, need * sizeof(int32_t)));
     }
-    lab2 = P<int32_t>(c->labels2) + (int64_t)first * c->max_s;
-    if (J == 1) lab2 = P<int32_t>(c->labels2);
+    L->lab[1] = J == 1 ? P<int32_t>(c->labels2) : P<int32_t>(c->labels2) + (int64_t)first * c->max_s;
   }
-  int32_t* const lab_arr[2] = {labels, lab2};
+  a.labels2 = L->lab[1];
+  return BM_OK;
+}
+
+// One Lloyd iteration (assignment, update, finalize) of every active job of
+// the batch over the tile map tm.
+int lloyd_launch(bm_ctx* c, LloydSetup& L, const BatchView& b, const TileMap& tm, int64_t max_size,
+                 int prof_slot) {
+  const int J = b.njobs;
+  L.a.tile_pts = tm.tile_pts;
+  // the tile arrays may have been reallocated by upload_tiles since the setup
+  L.a.tile_job = P<int32_t>(c->tile_job);
+  L.a.tile_idx = P<int32_t>(c->tile_idx);
+  if (tm.total > c->tile_cap) return c->fail(BM_E_STATE, "tile map not uploaded");
+  if (prof_slot >= 0) HIP_TRY(c, hipEventRecord(c->pev[2 * prof_slot], c->stream));
+  if (L.wide) {
+    HIP_TRY(c, bm::launch_assign_wide(c->stream, L.a, tm.total, true));
+    HIP_TRY(c, bm::launch_update_wide(c->stream, b.S, b.S_stride, b.ld, b.n, b.cp, b.k, L.a.s, L.js,
+                                      J, max_size, L.lab[0], L.lab[1], L.lab_stride, L.acc, L.cnt,
+                                      L.a.scale));
+  } else {
+    HIP_TRY(c, bm::launch_assign(c->stream, L.a, tm.total, true));
+  }
+  if (prof_slot >= 0) HIP_TRY(c, hipEventRecord(c->pev[2 * prof_slot + 1], c->stream));
+  if (L.wide)
+    HIP_TRY(c, bm::launch_finalize_wide(c->stream, L.f, J));
+  else
+    HIP_TRY(c, bm::launch_finalize(c->stream, L.f, J));
+  return BM_OK;
+}
+
+// Run Lloyd on every job of the batch from the centroids in Cp (slots
+// first..first+njobs-1).  Leaves the final centroids in Cp, the job states in
+// js, degenerate flags in deg_work and the final labels in `labels` (or in
+// the workspace label buffer when labels is null).
+int lloyd_batch(bm_ctx* c, const BatchView& b, int max_iter, double tol, int32_t* labels,
+                int64_t lab_stride, bool accept = false, std::vector<JobState>* out = nullptr) {
+  const int J = b.njobs, first = b.first, k = b.k, cp = b.cp;
+  LloydSetup L;
+  BM_TRY(lloyd_setup(c, b, max_iter, tol, labels, lab_stride, accept, &L));
+  TileMap tm = make_tiles(b.sizes, choose_tile_pts(b.sizes));
+  BM_TRY(upload_tiles(c, tm));
+  BM_TRY(upload(c, P<int64_t>(c->sizes) + first, b.sizes.data(), J * sizeof(int64_t)));
+  HIP_TRY(c, bm::launch_job_init(c->stream, L.js, P<int64_t>(c->sizes) + first, J, k, cp, L.acc,
+                                 L.cnt, P<float>(c->Cp) + (int64_t)first * k * cp,
+                                 P<float>(c->cn) + (int64_t)first * k));
   int64_t max_size = 0;
   for (int64_t v : b.sizes) max_size = std::max(max_size, v);
 
@@ -419,26 +475,9 @@ int lloyd_batch(bm_ctx* c, const BatchView& b, int max_iter, double tol, int32_t
         c->pev.push_back(e);
       }
     }
-    for (int q = 0; q < todo; ++q) {
-      if (c->prof) HIP_TRY(c, hipEventRecord(c->pev[2 * q], c->stream));
-      if (wide) {
-        const int qa = launched + q;  // assignment index of this launch
-        a.labels = lab_arr[qa & 1];
-        HIP_TRY(c, bm::launch_assign_wide(c->stream, a, tm.total, true));
-        HIP_TRY(c, bm::launch_update_wide(c->stream, b.S, b.S_stride, b.ld, b.n, cp, k, a.s, js, J,
-                                          max_size, qa == 0 ? nullptr : lab_arr[(qa + 1) & 1],
-                                          lab_arr[qa & 1], lab_stride, acc, cnt, a.scale));
-      } else {
-        HIP_TRY(c, bm::launch_assign(c->stream, a, tm.total, true));
-      }
-      if (c->prof) HIP_TRY(c, hipEventRecord(c->pev[2 * q + 1], c->stream));
-      if (wide)
-        HIP_TRY(c, bm::launch_finalize_wide(c->stream, f, J));
-      else
-        HIP_TRY(c, bm::launch_finalize(c->stream, f, J));
-    }
+    for (int q = 0; q < todo; ++q) BM_TRY(lloyd_launch(c, L, b, tm, max_size, c->prof ? q : -1));
     launched += todo;
-    BM_TRY(readback(c, js, J * sizeof(JobState), hs.data()));
+    BM_TRY(readback(c, L.js, J * sizeof(JobState), hs.data()));
     if (c->prof) {
       for (int q = 0; q < todo; ++q) {
         float ms_a = 0.f;
@@ -464,10 +503,11 @@ int lloyd_batch(bm_ctx* c, const BatchView& b, int max_iter, double tol, int32_t
     }
     if (!any) {
       if (out) *out = hs;
-      if (wide) {  // final labels of a job whose last assignment was odd are in L[1]
+      if (L.wide) {  // final labels of a job whose last assignment was odd are in lab[1]
         for (int j = 0; j < J; ++j)
           if (hs[j].iter & 1)
-            HIP_TRY(c, hipMemcpyAsync(labels + (int64_t)j * lab_stride, lab2 + (int64_t)j * lab_stride,
+            HIP_TRY(c, hipMemcpyAsync(L.lab[0] + (int64_t)j * L.lab_stride,
+                                      L.lab[1] + (int64_t)j * L.lab_stride,
                                       (size_t)b.sizes[j] * sizeof(int32_t), hipMemcpyDeviceToDevice,
                                       c->stream));
       }
@@ -476,8 +516,7 @@ int lloyd_batch(bm_ctx* c, const BatchView& b, int max_iter, double tol, int32_t
     if (launched >= max_iter + 1) return c->fail(BM_E_STATE, "Lloyd did not stop after %d steps", launched);
     if (shrink) {
       // fewer points left: smaller tiles spread them over more compute units
-      a.tile_pts = choose_tile_pts(live);
-      tm = make_tiles(live, a.tile_pts);
+      tm = make_tiles(live, choose_tile_pts(live));
       BM_TRY(upload_tiles(c, tm));
     }
     chunk = std::min(chunk * 2, 16);
@@ -909,6 +948,324 @@ int validate_params(bm_ctx* c, const bm_params* p) {
   return BM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Serving loop (bm_serve): single-pass jobs of competing workers, batched
+// continuously.  Every (dataset, k) has its own context whose job slots hold
+// the running jobs; every (dataset, k, worker) has an incumbent in a device
+// store for the whole call.
+// ---------------------------------------------------------------------------
+struct ServeWorker {
+  int d = 0, k = 0, w = 0, group = 0;
+  uint32_t rng_worker = 0;
+  int64_t off_c = 0, off_deg = 0;  // offsets in the incumbent store
+  double fhat = std::numeric_limits<double>::infinity();
+  int ndeg = 0;
+  int64_t s_prev = -1;
+  uint64_t passes = 0;
+  bool busy = false;
+  std::deque<int> queue;  // arrived jobs, arrival order
+};
+
+struct ServeGroup {
+  int d = 0, k = 0, n = 0, cp = 0;
+  bm_ctx* c = nullptr;
+  int slots = 0;
+  int64_t s_max = 0;
+  int64_t jobs = 0;
+  std::vector<int> slot_job;   // job of each slot, -1 when free
+  std::vector<int64_t> sizes;  // its sample size, 0 when free
+  LloydSetup L;
+  int running = 0;
+};
+
+// Device bytes one running job of sample size s uses (sample, indices, two
+// label arrays, K-means++ D slots and tile sums, chunk partials, centroid
+// state).
+int64_t serve_job_bytes(int64_t s, int n, int k) {
+  const int64_t cp = round_up4(n), ch = (s + bm::kWG - 1) / bm::kWG;
+  return s * (cp * 4 + 4 + 8 + 16) + ch * (4 * 8 + 12) + (int64_t)k * (cp * 12 + n * 4 + 16) + 1024;
+}
+
+struct ServeState {
+  std::vector<ServeGroup> groups;
+  float* store_c = nullptr;
+  uint8_t* store_deg = nullptr;
+  ~ServeState() {
+    for (ServeGroup& g : groups)
+      if (g.c) bm_destroy(g.c);
+    if (store_c) (void)hipFree(store_c);
+    if (store_deg) (void)hipFree(store_deg);
+  }
+};
+
+int serve_admit(bm_ctx* c, ServeState& st, ServeWorker& W, const bm_dataset& ds, const bm_job& job,
+                const bm_serve_params& sp, int q) {
+  ServeGroup& G = st.groups[W.group];
+  bm_ctx* gc = G.c;
+  const int k = G.k, n = G.n, cp = G.cp;
+  const int64_t s = job.s, Sj = gc->max_s * cp;
+  float* Sq = P<float>(gc->S) + q * Sj;
+  hipStream_t str = gc->stream;
+  const uint64_t g = W.passes;
+  uint64_t rk[4];
+  // the worker's incumbent into the slot
+  HIP_TRY(c, hipMemcpyAsync(P<float>(gc->Cinc) + (int64_t)q * k * n, st.store_c + W.off_c,
+                            (size_t)k * n * sizeof(float), hipMemcpyDeviceToDevice, str));
+  HIP_TRY(c, hipMemcpyAsync(P<uint8_t>(gc->deg_inc) + (int64_t)q * k, st.store_deg + W.off_deg,
+                            (size_t)k, hipMemcpyDeviceToDevice, str));
+  BatchView b;
+  b.first = q;
+  b.njobs = 1;
+  b.n = n;
+  b.cp = cp;
+  b.k = k;
+  b.S = Sq;
+  b.S_stride = Sj;
+  b.ld = cp;
+  b.sizes = {s};
+  BM_TRY(upload(gc, P<int64_t>(gc->sizes) + q, &s, sizeof s));
+  // re-evaluate the incumbent on a fresh sample of the new size (Algorithm 1; Section 4.2)
+  if (std::isfinite(W.fhat) && s != W.s_prev) {
+    round_keys((uint64_t)ds.m, sp.seed, W.rng_worker, BM_PURPOSE_RECALC, g, rk);
+    BM_TRY(upload(gc, P<uint64_t>(gc->rkeys) + 4 * q, rk, sizeof rk));
+    HIP_TRY(c, bm::launch_sample(str, ds.X, ds.m, n, 1, s, P<int64_t>(gc->sizes) + q,
+                                 P<uint64_t>(gc->rkeys) + 4 * q, P<int32_t>(gc->idx) + q * gc->max_s,
+                                 gc->max_s, Sq, Sj, cp));
+    HIP_TRY(c, bm::launch_pad_centroids(str, P<float>(gc->Cinc) + (int64_t)q * k * n, (int64_t)k * n, n,
+                                        cp, k, 1, P<float>(gc->Cp) + (int64_t)q * k * cp,
+                                        (int64_t)k * cp, P<float>(gc->cn) + (int64_t)q * k, k));
+    BM_TRY(objective_batch(gc, b, nullptr, 0, gc->max_chunks, false));
+    BM_TRY(readback(gc, P<double>(gc->fjob) + q, sizeof(double), &W.fhat));
+  }
+  BM_TRY(upload(gc, P<double>(gc->fhat) + q, &W.fhat, sizeof(double)));
+  // the pass's sample, the incumbent as the working copy, K-means++ for its degenerate centroids
+  round_keys((uint64_t)ds.m, sp.seed, W.rng_worker, BM_PURPOSE_SAMPLE, g, rk);
+  BM_TRY(upload(gc, P<uint64_t>(gc->rkeys) + 4 * q, rk, sizeof rk));
+  HIP_TRY(c, bm::launch_sample(str, ds.X, ds.m, n, 1, s, P<int64_t>(gc->sizes) + q,
+                               P<uint64_t>(gc->rkeys) + 4 * q, P<int32_t>(gc->idx) + q * gc->max_s,
+                               gc->max_s, Sq, Sj, cp));
+  HIP_TRY(c, bm::launch_copy_incumbent(str, P<float>(gc->Cinc) + (int64_t)q * k * n,
+                                       P<uint8_t>(gc->deg_inc) + (int64_t)q * k, n, cp, k, 1,
+                                       P<float>(gc->Cp) + (int64_t)q * k * cp,
+                                       P<uint8_t>(gc->deg_work) + (int64_t)q * k));
+  const uint64_t sw[2] = {sp.seed, (uint64_t)W.rng_worker};
+  KppBatch kb{sw, g, sp.n_candidates, W.ndeg, nullptr};
+  BM_TRY(kpp_batch(gc, b, kb));
+  // Lloyd state of the slot
+  HIP_TRY(c, bm::launch_job_init(str, G.L.js + q, P<int64_t>(gc->sizes) + q, 1, k, cp, G.L.acc + (int64_t)q * k * cp,
+                                 G.L.cnt + (int64_t)q * k, P<float>(gc->Cp) + (int64_t)q * k * cp,
+                                 P<float>(gc->cn) + (int64_t)q * k));
+  return BM_OK;
+}
+
+int serve_impl(bm_ctx* c, const bm_dataset* ds, int nds, const bm_job* jobs, int njobs,
+               const bm_serve_params& sp, bm_job_result* res, bm_serve_stats* stats) {
+  using clock = std::chrono::steady_clock;
+  ServeState st;
+  std::vector<ServeWorker> workers;
+  std::map<std::tuple<int, int, int>, int> wmap;
+  std::map<std::pair<int, int>, int> gmap;
+  std::vector<int> job_worker(njobs);
+  for (int j = 0; j < njobs; ++j) {
+    const bm_job& jb = jobs[j];
+    const auto key = std::make_tuple(jb.dataset, jb.k, jb.worker);
+    auto it = wmap.find(key);
+    if (it == wmap.end()) {
+      ServeWorker W;
+      W.d = jb.dataset;
+      W.k = jb.k;
+      W.w = jb.worker;
+      W.rng_worker = ((uint32_t)jb.dataset << 20) | ((uint32_t)jb.k << 10) | (uint32_t)jb.worker;
+      W.ndeg = jb.k;
+      const auto gk = std::make_pair(jb.dataset, jb.k);
+      auto gi = gmap.find(gk);
+      if (gi == gmap.end()) {
+        ServeGroup G;
+        G.d = jb.dataset;
+        G.k = jb.k;
+        G.n = ds[jb.dataset].n;
+        G.cp = round_up4(G.n);
+        gi = gmap.emplace(gk, (int)st.groups.size()).first;
+        st.groups.push_back(std::move(G));
+      }
+      W.group = gi->second;
+      it = wmap.emplace(key, (int)workers.size()).first;
+      workers.push_back(std::move(W));
+    }
+    job_worker[j] = it->second;
+    ServeGroup& G = st.groups[workers[it->second].group];
+    G.s_max = std::max(G.s_max, jb.s);
+    G.jobs += 1;
+  }
+  // slots per group within the budget, in proportion to the group's jobs
+  int64_t total_slot_bytes = 0;
+  for (ServeGroup& G : st.groups) {
+    const int64_t per = serve_job_bytes(G.s_max, G.n, G.k);
+    const double share = (double)sp.budget_bytes * (double)G.jobs / (double)njobs;
+    if (per > sp.budget_bytes)
+      return c->fail(BM_E_ARG, "budget too small for a job of dataset %d, k = %d", G.d, G.k);
+    int64_t slots = (int64_t)(share / (double)per);
+    slots = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(slots, sp.max_slots), G.jobs));
+    G.slots = (int)slots;
+    total_slot_bytes += slots * per;
+  }
+  // incumbent store: all centroids degenerate, f = +inf
+  int64_t nc = 0, ndg = 0;
+  for (ServeWorker& W : workers) {
+    W.off_c = nc;
+    W.off_deg = ndg;
+    nc += (int64_t)W.k * ds[W.d].n;
+    ndg += W.k;
+  }
+  HIP_TRY(c, hipMalloc(&st.store_c, (size_t)nc * sizeof(float)));
+  HIP_TRY(c, hipMalloc(&st.store_deg, (size_t)ndg));
+  HIP_TRY(c, hipMemsetAsync(st.store_c, 0, (size_t)nc * sizeof(float), c->stream));
+  HIP_TRY(c, hipMemsetAsync(st.store_deg, 1, (size_t)ndg, c->stream));
+  // one context per (dataset, k): workspace for its slots, data scales, idle job states
+  for (ServeGroup& G : st.groups) {
+    int rc = bm_create(c->device, c->stream, &G.c);
+    if (rc != BM_OK) return c->fail(rc, "serving workspace: context creation failed");
+    rc = reserve_impl(G.c, G.s_max, G.n, G.k, G.slots);
+    if (rc != BM_OK) return c->fail(rc, "serving workspace: %s", G.c->err.c_str());
+    const bm_dataset& D = ds[G.d];
+    rc = compute_scales(G.c, D.X, D.m, D.n, D.n, G.cp, G.s_max);
+    if (rc != BM_OK) return c->fail(rc, "%s", G.c->err.c_str());
+    HIP_TRY(c, hipMemsetAsync(G.c->js.p, 0, (size_t)G.slots * sizeof(JobState), c->stream));
+    G.slot_job.assign(G.slots, -1);
+    G.sizes.assign(G.slots, 0);
+    BatchView b;
+    b.first = 0;
+    b.njobs = G.slots;
+    b.n = G.n;
+    b.cp = G.cp;
+    b.k = G.k;
+    b.S = P<float>(G.c->S);
+    b.S_stride = G.c->max_s * G.cp;
+    b.ld = G.cp;
+    rc = lloyd_setup(G.c, b, sp.max_iter, sp.tol, nullptr, 0, true, &G.L);
+    if (rc != BM_OK) return c->fail(rc, "%s", G.c->err.c_str());
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+
+  std::vector<int> order(njobs);
+  for (int j = 0; j < njobs; ++j) order[j] = j;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return jobs[a].arrival < jobs[b].arrival; });
+  const auto t0 = clock::now();
+  auto elapsed = [&]() { return std::chrono::duration<double>(clock::now() - t0).count(); };
+  int next = 0, done = 0;
+  int64_t inflight = 0, steps = 0, peak_running = 0, peak_bytes = 0, running = 0;
+  std::vector<JobState> hs;
+  while (done < njobs) {
+    const double now = elapsed();
+    while (next < njobs && (!sp.paced || jobs[order[next]].arrival <= now)) {
+      const int j = order[next++];
+      workers[job_worker[j]].queue.push_back(j);
+    }
+    // admissions, earliest arrival first
+    std::vector<int> heads;
+    for (ServeWorker& W : workers)
+      if (!W.busy && !W.queue.empty()) heads.push_back(W.queue.front());
+    std::stable_sort(heads.begin(), heads.end(), [&](int a, int b) {
+      return jobs[a].arrival < jobs[b].arrival || (jobs[a].arrival == jobs[b].arrival && a < b);
+    });
+    int admitted = 0;
+    for (int j : heads) {
+      ServeWorker& W = workers[job_worker[j]];
+      ServeGroup& G = st.groups[W.group];
+      const int64_t bytes = serve_job_bytes(jobs[j].s, G.n, G.k);
+      if (G.running >= G.slots || inflight + bytes > sp.budget_bytes) continue;
+      int q = 0;
+      while (G.slot_job[q] >= 0) ++q;
+      BM_TRY(serve_admit(c, st, W, ds[W.d], jobs[j], sp, q));
+      W.queue.pop_front();
+      W.busy = true;
+      G.slot_job[q] = j;
+      G.sizes[q] = jobs[j].s;
+      G.running += 1;
+      running += 1;
+      inflight += bytes;
+      res[j].admitted = elapsed();
+      ++admitted;
+    }
+    peak_running = std::max(peak_running, running);
+    peak_bytes = std::max(peak_bytes, inflight);
+    if (running == 0) {
+      if (next < njobs && sp.paced) {  // idle until the next arrival
+        const double wait = jobs[order[next]].arrival - elapsed();
+        if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(std::min(wait, 0.01)));
+        continue;
+      }
+      if (admitted == 0) return c->fail(BM_E_STATE, "serving loop made no progress");
+      continue;
+    }
+    // one Lloyd iteration of every running job
+    for (ServeGroup& G : st.groups) {
+      if (G.running == 0) continue;
+      TileMap tm = make_tiles(G.sizes, choose_tile_pts(G.sizes));
+      BM_TRY(upload_tiles(G.c, tm));
+      BM_TRY(upload(G.c, P<int64_t>(G.c->sizes), G.sizes.data(), G.slots * sizeof(int64_t)));
+      BatchView b;
+      b.first = 0;
+      b.njobs = G.slots;
+      b.n = G.n;
+      b.cp = G.cp;
+      b.k = G.k;
+      b.S = P<float>(G.c->S);
+      b.S_stride = G.c->max_s * G.cp;
+      b.ld = G.cp;
+      b.sizes = G.sizes;
+      BM_TRY(lloyd_launch(G.c, G.L, b, tm, G.s_max, -1));
+    }
+    ++steps;
+    // finished jobs leave; an accepted result becomes the worker's incumbent
+    for (ServeGroup& G : st.groups) {
+      if (G.running == 0) continue;
+      hs.resize(G.slots);
+      BM_TRY(readback(G.c, G.L.js, G.slots * sizeof(JobState), hs.data()));
+      for (int q = 0; q < G.slots; ++q) {
+        const int j = G.slot_job[q];
+        if (j < 0 || hs[q].active) continue;
+        ServeWorker& W = workers[job_worker[j]];
+        bm_job_result& r = res[j];
+        r.f = hs[q].f;
+        r.iters = hs[q].iter;
+        r.accepted = hs[q].accepted;
+        r.ndeg = hs[q].ndeg;
+        if (hs[q].accepted) {
+          HIP_TRY(c, hipMemcpyAsync(st.store_c + W.off_c, P<float>(G.c->Cinc) + (int64_t)q * G.k * G.n,
+                                    (size_t)G.k * G.n * sizeof(float), hipMemcpyDeviceToDevice,
+                                    c->stream));
+          HIP_TRY(c, hipMemcpyAsync(st.store_deg + W.off_deg, P<uint8_t>(G.c->deg_inc) + (int64_t)q * G.k,
+                                    (size_t)G.k, hipMemcpyDeviceToDevice, c->stream));
+          W.fhat = hs[q].f;
+          W.ndeg = hs[q].ndeg;
+        }
+        r.f_incumbent = W.fhat;
+        r.finished = elapsed();
+        W.s_prev = jobs[j].s;
+        W.passes += 1;
+        W.busy = false;
+        G.slot_job[q] = -1;
+        G.sizes[q] = 0;
+        G.running -= 1;
+        running -= 1;
+        inflight -= serve_job_bytes(jobs[j].s, G.n, G.k);
+        ++done;
+      }
+    }
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (stats) {
+    stats->seconds = elapsed();
+    stats->steps = steps;
+    stats->peak_running = peak_running;
+    stats->peak_bytes = peak_bytes;
+    stats->slot_bytes = total_slot_bytes;
+  }
+  return BM_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1139,6 +1496,39 @@ BM_API int bm_get_stats(bm_ctx* c, bm_stats* out) {
 // ---------------------------------------------------------------------------
 // Algorithm 1
 // ---------------------------------------------------------------------------
+BM_API int bm_serve(bm_ctx* c, const bm_dataset* datasets, int32_t nds, const bm_job* jobs,
+                    int32_t njobs, const bm_serve_params* params, bm_job_result* results,
+                    bm_serve_stats* stats) {
+  if (!c) return BM_E_ARG;
+  if (!datasets || !jobs || !params || !results || nds < 1 || nds > 16 || njobs < 0)
+    return c->fail(BM_E_ARG, "bm_serve: need datasets (1..16), jobs, params and results");
+  const bm_serve_params& sp = *params;
+  if (sp.max_slots < 1 || sp.max_iter < 0 || !(sp.tol >= 0.0) || sp.n_candidates < 1 ||
+      sp.n_candidates > 3 || sp.budget_bytes < 1)
+    return c->fail(BM_E_ARG, "bm_serve: need max_slots >= 1, max_iter >= 0, tol >= 0, "
+                             "n_candidates in 1..3, budget > 0");
+  for (int d = 0; d < nds; ++d) {
+    const bm_dataset& D = datasets[d];
+    if (!D.X || D.m < 1 || D.m >= (1ll << 31)) return c->fail(BM_E_ARG, "dataset %d: need X and 1 <= m < 2^31", d);
+  }
+  for (int j = 0; j < njobs; ++j) {
+    const bm_job& jb = jobs[j];
+    if (jb.dataset < 0 || jb.dataset >= nds) return c->fail(BM_E_ARG, "job %d: dataset out of range", j);
+    const bm_dataset& D = datasets[jb.dataset];
+    if (jb.k < 1 || jb.k >= 1024 || jb.worker < 0 || jb.worker >= 1024)
+      return c->fail(BM_E_ARG, "job %d: need 1 <= k < 1024 and 0 <= worker < 1024", j);
+    if (jb.s < jb.k || jb.s > D.m) return c->fail(BM_E_ARG, "job %d: need k <= s <= m", j);
+    if (!(jb.arrival >= 0.0)) return c->fail(BM_E_ARG, "job %d: arrival must be >= 0", j);
+    BM_TRY(check_prec(c, jb.prec));
+    BM_TRY(check_dim(c, D.n, jb.k));
+  }
+  HIP_TRY(c, hipSetDevice(c->device));
+  std::memset(results, 0, (size_t)njobs * sizeof(bm_job_result));
+  if (stats) std::memset(stats, 0, sizeof *stats);
+  if (njobs == 0) return BM_OK;
+  return serve_impl(c, datasets, nds, jobs, njobs, sp, results, stats);
+}
+
 BM_API int bm_bigmeans_run(bm_ctx* c, const float* X, const bm_params* params, float* C_best_out,
                            int32_t* Y_out, bm_result* out, bm_trace_cb cb, void* user) {
   if (!c) return BM_E_ARG;

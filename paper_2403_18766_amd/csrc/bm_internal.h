@@ -59,6 +59,8 @@ struct AssignArgs {
   const float* cn;
   int64_t cn_stride;
   int32_t* labels;           // nullable; job j at labels + j*lab_stride
+  int32_t* labels2;          // wide-point Lloyd only (nullable): assignment q of a job writes
+                             // labels when q is even, labels2 when q is odd (q = its iter)
   int64_t lab_stride;
   double* tf;                // [job][max_chunks] objective partial of each 256-point chunk
   int32_t* tnear;            // [job][max_chunks] near-tie count of each chunk (nullable)
@@ -106,12 +108,12 @@ hipError_t launch_finalize(hipStream_t st, const FinalizeArgs& a, int32_t njobs)
 // ---- wide points, cp > kMaxRegDim (bm_wide.hip) ----
 // tile_pts must be a multiple of 256.
 hipError_t launch_assign_wide(hipStream_t st, const AssignArgs& a, int32_t ntiles, bool sums);
-// Fixed-point sums of the label changes lab_old -> lab_new (lab_old null on
-// the first assignment) for every active job.
+// Fixed-point sums of the label changes of every active job: its assignment
+// q = iter wrote lab[q % 2]; the previous one (none when q = 0) lab[(q+1) % 2].
 hipError_t launch_update_wide(hipStream_t st, const float* S, int64_t S_stride, int32_t ld,
                               int32_t n, int32_t cp, int32_t k, const int64_t* s,
                               const JobState* js, int32_t njobs, int64_t max_s,
-                              const int32_t* lab_old, const int32_t* lab_new, int64_t lab_stride,
+                              const int32_t* lab0, const int32_t* lab1, int64_t lab_stride,
                               unsigned long long* acc, int32_t* cnt, const double* scale);
 hipError_t launch_finalize_wide(hipStream_t st, const FinalizeArgs& a, int32_t njobs);
 // LDS bytes of the wide update kernel for k clusters.

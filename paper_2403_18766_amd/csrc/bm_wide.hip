@@ -93,7 +93,12 @@ struct WideShared {
 template <bool SUMS>
 __global__ __launch_bounds__(256, 2) void k_assign_wide(AssignArgs a) {
   const int job = a.tile_job[blockIdx.x];
-  if (a.st && !a.st[job].active) return;
+  int parity = 0;
+  if (a.st) {
+    const JobState st = a.st[job];
+    if (!st.active) return;
+    parity = st.iter & 1;
+  }
   const int64_t s = a.s[job];
   const int64_t t0 = (int64_t)a.tile_idx[blockIdx.x] * a.tile_pts;
   const int64_t t1 = min(s, t0 + (int64_t)a.tile_pts);
@@ -101,7 +106,8 @@ __global__ __launch_bounds__(256, 2) void k_assign_wide(AssignArgs a) {
   const float* __restrict__ S = a.S + job * a.S_stride;
   const float* __restrict__ C = a.Cp + job * a.C_stride;
   const float* __restrict__ cn = a.cn + job * a.cn_stride;
-  int32_t* __restrict__ lab = a.labels ? a.labels + job * a.lab_stride : nullptr;
+  int32_t* const lbase = (parity && a.labels2) ? a.labels2 : a.labels;
+  int32_t* __restrict__ lab = lbase ? lbase + job * a.lab_stride : nullptr;
   double* tfj = a.tf + (int64_t)job * a.max_chunks;
   const bool want_near = a.tnear != nullptr;
   const int vec = a.vec;
@@ -283,8 +289,8 @@ struct UpdateArgs {
   int32_t ld, n, cp, k;
   const int64_t* s;
   const JobState* st;
-  const int32_t* lab_old;  // nullable: first assignment
-  const int32_t* lab_new;
+  const int32_t* lab0;     // assignment q of a job (q = its iter) wrote lab[q % 2]
+  const int32_t* lab1;
   int64_t lab_stride;
   unsigned long long* acc;  // [job][k][cp]
   int32_t* cnt;             // [job][k]
@@ -293,7 +299,9 @@ struct UpdateArgs {
 
 __global__ __launch_bounds__(256) void k_update_wide(UpdateArgs u) {
   const int job = blockIdx.z;
-  if (u.st && !u.st[job].active) return;
+  const JobState st = u.st[job];
+  if (!st.active) return;
+  const int q = st.iter;
   const int64_t s = u.s[job];
   const int64_t r0 = (int64_t)blockIdx.y * kUpdPts;
   if (r0 >= s) return;
@@ -307,8 +315,8 @@ __global__ __launch_bounds__(256) void k_update_wide(UpdateArgs u) {
   for (int e = threadIdx.x; e < k; e += 256) lcnt[e] = 0;
   __syncthreads();
   const float* S = u.S + job * u.S_stride;
-  const int32_t* ln = u.lab_new + job * u.lab_stride;
-  const int32_t* lo = u.lab_old ? u.lab_old + job * u.lab_stride : nullptr;
+  const int32_t* ln = ((q & 1) ? u.lab1 : u.lab0) + job * u.lab_stride;
+  const int32_t* lo = q == 0 ? nullptr : ((q & 1) ? u.lab0 : u.lab1) + job * u.lab_stride;
   const bool counts = blockIdx.x == 0;
   int changed = 0;
   // one thread per point, the slice's dimensions in order
@@ -438,7 +446,7 @@ size_t update_wide_lds(int32_t k) {
 hipError_t launch_update_wide(hipStream_t st, const float* S, int64_t S_stride, int32_t ld,
                               int32_t n, int32_t cp, int32_t k, const int64_t* s,
                               const JobState* js, int32_t njobs, int64_t max_s,
-                              const int32_t* lab_old, const int32_t* lab_new, int64_t lab_stride,
+                              const int32_t* lab0, const int32_t* lab1, int64_t lab_stride,
                               unsigned long long* acc, int32_t* cnt, const double* scale) {
   UpdateArgs u;
   u.S = S;
@@ -449,8 +457,8 @@ hipError_t launch_update_wide(hipStream_t st, const float* S, int64_t S_stride, 
   u.k = k;
   u.s = s;
   u.st = js;
-  u.lab_old = lab_old;
-  u.lab_new = lab_new;
+  u.lab0 = lab0;
+  u.lab1 = lab1;
   u.lab_stride = lab_stride;
   u.acc = acc;
   u.cnt = cnt;
