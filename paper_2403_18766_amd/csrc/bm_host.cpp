@@ -998,63 +998,138 @@ struct ServeState {
   }
 };
 
-int serve_admit(bm_ctx* c, ServeState& st, ServeWorker& W, const bm_dataset& ds, const bm_job& job,
-                const bm_serve_params& sp, int q) {
-  ServeGroup& G = st.groups[W.group];
+// Start the jobs `adm` (job, slot) of group G together: incumbents into their
+// slots, re-evaluation of incumbents whose size changed, the passes' samples,
+// K-means++ of every job's degenerate centroids in one batch over its slots,
+// and the jobs' Lloyd states.
+int serve_admit(bm_ctx* c, ServeState& st, std::vector<ServeWorker>& workers,
+                const std::vector<int>& job_worker, ServeGroup& G, const std::vector<std::pair<int, int>>& adm,
+                const bm_dataset& ds, const bm_job* jobs, const bm_serve_params& sp) {
   bm_ctx* gc = G.c;
-  const int k = G.k, n = G.n, cp = G.cp;
-  const int64_t s = job.s, Sj = gc->max_s * cp;
-  float* Sq = P<float>(gc->S) + q * Sj;
+  const int k = G.k, n = G.n, cp = G.cp, J = G.slots;
+  const int64_t Sj = gc->max_s * cp;
   hipStream_t str = gc->stream;
-  const uint64_t g = W.passes;
-  uint64_t rk[4];
-  // the worker's incumbent into the slot
-  HIP_TRY(c, hipMemcpyAsync(P<float>(gc->Cinc) + (int64_t)q * k * n, st.store_c + W.off_c,
-                            (size_t)k * n * sizeof(float), hipMemcpyDeviceToDevice, str));
-  HIP_TRY(c, hipMemcpyAsync(P<uint8_t>(gc->deg_inc) + (int64_t)q * k, st.store_deg + W.off_deg,
-                            (size_t)k, hipMemcpyDeviceToDevice, str));
-  BatchView b;
-  b.first = q;
-  b.njobs = 1;
-  b.n = n;
-  b.cp = cp;
-  b.k = k;
-  b.S = Sq;
-  b.S_stride = Sj;
-  b.ld = cp;
-  b.sizes = {s};
-  BM_TRY(upload(gc, P<int64_t>(gc->sizes) + q, &s, sizeof s));
-  // re-evaluate the incumbent on a fresh sample of the new size (Algorithm 1; Section 4.2)
-  if (std::isfinite(W.fhat) && s != W.s_prev) {
-    round_keys((uint64_t)ds.m, sp.seed, W.rng_worker, BM_PURPOSE_RECALC, g, rk);
-    BM_TRY(upload(gc, P<uint64_t>(gc->rkeys) + 4 * q, rk, sizeof rk));
-    HIP_TRY(c, bm::launch_sample(str, ds.X, ds.m, n, 1, s, P<int64_t>(gc->sizes) + q,
-                                 P<uint64_t>(gc->rkeys) + 4 * q, P<int32_t>(gc->idx) + q * gc->max_s,
-                                 gc->max_s, Sq, Sj, cp));
-    HIP_TRY(c, bm::launch_pad_centroids(str, P<float>(gc->Cinc) + (int64_t)q * k * n, (int64_t)k * n, n,
-                                        cp, k, 1, P<float>(gc->Cp) + (int64_t)q * k * cp,
-                                        (int64_t)k * cp, P<float>(gc->cn) + (int64_t)q * k, k));
-    BM_TRY(objective_batch(gc, b, nullptr, 0, gc->max_chunks, false));
-    BM_TRY(readback(gc, P<double>(gc->fjob) + q, sizeof(double), &W.fhat));
+  BatchView all;
+  all.first = 0;
+  all.njobs = J;
+  all.n = n;
+  all.cp = cp;
+  all.k = k;
+  all.S = P<float>(gc->S);
+  all.S_stride = Sj;
+  all.ld = cp;
+  std::vector<uint64_t> rk(4 * (size_t)J, 0);
+  std::vector<int64_t> sz(J, 0);
+  int64_t smax = 0;
+  for (const auto& jq : adm) {
+    const ServeWorker& W = workers[job_worker[jq.first]];
+    const int q = jq.second;
+    HIP_TRY(c, hipMemcpyAsync(P<float>(gc->Cinc) + (int64_t)q * k * n, st.store_c + W.off_c,
+                              (size_t)k * n * sizeof(float), hipMemcpyDeviceToDevice, str));
+    HIP_TRY(c, hipMemcpyAsync(P<uint8_t>(gc->deg_inc) + (int64_t)q * k, st.store_deg + W.off_deg,
+                              (size_t)k, hipMemcpyDeviceToDevice, str));
   }
-  BM_TRY(upload(gc, P<double>(gc->fhat) + q, &W.fhat, sizeof(double)));
-  // the pass's sample, the incumbent as the working copy, K-means++ for its degenerate centroids
-  round_keys((uint64_t)ds.m, sp.seed, W.rng_worker, BM_PURPOSE_SAMPLE, g, rk);
-  BM_TRY(upload(gc, P<uint64_t>(gc->rkeys) + 4 * q, rk, sizeof rk));
-  HIP_TRY(c, bm::launch_sample(str, ds.X, ds.m, n, 1, s, P<int64_t>(gc->sizes) + q,
-                               P<uint64_t>(gc->rkeys) + 4 * q, P<int32_t>(gc->idx) + q * gc->max_s,
-                               gc->max_s, Sq, Sj, cp));
-  HIP_TRY(c, bm::launch_copy_incumbent(str, P<float>(gc->Cinc) + (int64_t)q * k * n,
-                                       P<uint8_t>(gc->deg_inc) + (int64_t)q * k, n, cp, k, 1,
-                                       P<float>(gc->Cp) + (int64_t)q * k * cp,
-                                       P<uint8_t>(gc->deg_work) + (int64_t)q * k));
-  const uint64_t sw[2] = {sp.seed, (uint64_t)W.rng_worker};
-  KppBatch kb{sw, g, sp.n_candidates, W.ndeg, nullptr};
-  BM_TRY(kpp_batch(gc, b, kb));
-  // Lloyd state of the slot
-  HIP_TRY(c, bm::launch_job_init(str, G.L.js + q, P<int64_t>(gc->sizes) + q, 1, k, cp, G.L.acc + (int64_t)q * k * cp,
-                                 G.L.cnt + (int64_t)q * k, P<float>(gc->Cp) + (int64_t)q * k * cp,
-                                 P<float>(gc->cn) + (int64_t)q * k));
+  // re-evaluate incumbents whose sample size changed (Algorithm 1; Section 4.2)
+  std::vector<int> re;
+  for (size_t i = 0; i < adm.size(); ++i) {
+    const ServeWorker& W = workers[job_worker[adm[i].first]];
+    if (std::isfinite(W.fhat) && jobs[adm[i].first].s != W.s_prev) re.push_back((int)i);
+  }
+  if (!re.empty()) {
+    for (int i : re) {
+      const int j = adm[i].first, q = adm[i].second;
+      const ServeWorker& W = workers[job_worker[j]];
+      sz[q] = jobs[j].s;
+      smax = std::max(smax, sz[q]);
+      round_keys((uint64_t)ds.m, sp.seed, W.rng_worker, BM_PURPOSE_RECALC, W.passes, &rk[4 * q]);
+      HIP_TRY(c, bm::launch_pad_centroids(str, P<float>(gc->Cinc) + (int64_t)q * k * n, (int64_t)k * n,
+                                          n, cp, k, 1, P<float>(gc->Cp) + (int64_t)q * k * cp,
+                                          (int64_t)k * cp, P<float>(gc->cn) + (int64_t)q * k, k));
+    }
+    BM_TRY(upload(gc, P<int64_t>(gc->sizes), sz.data(), J * sizeof(int64_t)));
+    BM_TRY(upload(gc, P<uint64_t>(gc->rkeys), rk.data(), 4 * (size_t)J * sizeof(uint64_t)));
+    HIP_TRY(c, bm::launch_sample(str, ds.X, ds.m, n, J, smax, P<int64_t>(gc->sizes),
+                                 P<uint64_t>(gc->rkeys), P<int32_t>(gc->idx), gc->max_s,
+                                 P<float>(gc->S), Sj, cp));
+    all.sizes = sz;
+    BM_TRY(objective_batch(gc, all, nullptr, 0, gc->max_chunks, false));
+    std::vector<double> fr(J);
+    BM_TRY(readback(gc, P<double>(gc->fjob), J * sizeof(double), fr.data()));
+    for (int i : re) workers[job_worker[adm[i].first]].fhat = fr[adm[i].second];
+  }
+  // the passes' samples; incumbents as working copies; f_hat of every slot
+  std::fill(sz.begin(), sz.end(), 0);
+  std::fill(rk.begin(), rk.end(), 0);
+  smax = 0;
+  std::vector<uint64_t> sw(2 * (size_t)J, 0), gs(J, 0);
+  std::vector<int32_t> slots;
+  int steps = 0;
+  for (const auto& jq : adm) {
+    const int j = jq.first, q = jq.second;
+    const ServeWorker& W = workers[job_worker[j]];
+    sz[q] = jobs[j].s;
+    smax = std::max(smax, sz[q]);
+    round_keys((uint64_t)ds.m, sp.seed, W.rng_worker, BM_PURPOSE_SAMPLE, W.passes, &rk[4 * q]);
+    sw[2 * q] = sp.seed;
+    sw[2 * q + 1] = W.rng_worker;
+    gs[q] = W.passes;
+    slots.push_back(q);
+    steps = std::max(steps, W.ndeg);
+    BM_TRY(upload(gc, P<double>(gc->fhat) + q, &W.fhat, sizeof(double)));
+    HIP_TRY(c, bm::launch_copy_incumbent(str, P<float>(gc->Cinc) + (int64_t)q * k * n,
+                                         P<uint8_t>(gc->deg_inc) + (int64_t)q * k, n, cp, k, 1,
+                                         P<float>(gc->Cp) + (int64_t)q * k * cp,
+                                         P<uint8_t>(gc->deg_work) + (int64_t)q * k));
+  }
+  BM_TRY(upload(gc, P<int64_t>(gc->sizes), sz.data(), J * sizeof(int64_t)));
+  BM_TRY(upload(gc, P<uint64_t>(gc->rkeys), rk.data(), 4 * (size_t)J * sizeof(uint64_t)));
+  HIP_TRY(c, bm::launch_sample(str, ds.X, ds.m, n, J, smax, P<int64_t>(gc->sizes),
+                               P<uint64_t>(gc->rkeys), P<int32_t>(gc->idx), gc->max_s,
+                               P<float>(gc->S), Sj, cp));
+  // K-means++ of the degenerate centroids, all admitted slots in one batch
+  if (steps > 0) {
+    const int A = (int)slots.size();
+    BM_TRY(upload(gc, P<int32_t>(gc->rflags), slots.data(), A * sizeof(int32_t)));
+    BM_TRY(upload(gc, P<uint64_t>(gc->seed_worker), sw.data(), 2 * (size_t)J * sizeof(uint64_t)));
+    BM_TRY(upload(gc, P<uint64_t>(gc->gs), gs.data(), J * sizeof(uint64_t)));
+    bm::KppArgs a{};
+    a.S = P<float>(gc->S);
+    a.S_stride = Sj;
+    a.ld = cp;
+    a.n = n;
+    a.cp = cp;
+    a.k = k;
+    a.ndt_max = (int32_t)gc->max_chunks;
+    a.njobs = gc->max_jobs;
+    a.s = P<int64_t>(gc->sizes);
+    a.Cp = P<float>(gc->Cp);
+    a.C_stride = (int64_t)k * cp;
+    a.deg = P<uint8_t>(gc->deg_work);
+    a.D = P<float>(gc->D);
+    a.D_slot_stride = (int64_t)gc->max_jobs * gc->max_s;
+    a.D_job_stride = gc->max_s;
+    a.Dt = P<double>(gc->Dt);
+    a.ks = P<KppState>(gc->ks);
+    a.todo = P<int32_t>(gc->todo);
+    a.picks = nullptr;
+    a.seed_worker = P<uint64_t>(gc->seed_worker);
+    a.g = 0;
+    a.gs = P<uint64_t>(gc->gs);
+    a.n_cand = sp.n_candidates;
+    a.job_slot = P<int32_t>(gc->rflags);
+    HIP_TRY(c, bm::launch_kpp_setup(str, a, A));
+    HIP_TRY(c, bm::launch_kpp_init(str, a, A, smax));
+    for (int step = 0; step < steps; ++step) {
+      HIP_TRY(c, bm::launch_kpp_step(str, a, A));
+      HIP_TRY(c, bm::launch_kpp_pot(str, a, A, smax));
+    }
+    HIP_TRY(c, bm::launch_kpp_step(str, a, A));  // commits the last step
+  }
+  // Lloyd state of every admitted slot
+  for (int q : slots)
+    HIP_TRY(c, bm::launch_job_init(str, G.L.js + q, P<int64_t>(gc->sizes) + q, 1, k, cp,
+                                   G.L.acc + (int64_t)q * k * cp, G.L.cnt + (int64_t)q * k,
+                                   P<float>(gc->Cp) + (int64_t)q * k * cp, P<float>(gc->cn) + (int64_t)q * k));
   return BM_OK;
 }
 
@@ -1170,6 +1245,7 @@ int serve_impl(bm_ctx* c, const bm_dataset* ds, int nds, const bm_job* jobs, int
       return jobs[a].arrival < jobs[b].arrival || (jobs[a].arrival == jobs[b].arrival && a < b);
     });
     int admitted = 0;
+    std::vector<std::vector<std::pair<int, int>>> adm(st.groups.size());
     for (int j : heads) {
       ServeWorker& W = workers[job_worker[j]];
       ServeGroup& G = st.groups[W.group];
@@ -1177,7 +1253,7 @@ int serve_impl(bm_ctx* c, const bm_dataset* ds, int nds, const bm_job* jobs, int
       if (G.running >= G.slots || inflight + bytes > sp.budget_bytes) continue;
       int q = 0;
       while (G.slot_job[q] >= 0) ++q;
-      BM_TRY(serve_admit(c, st, W, ds[W.d], jobs[j], sp, q));
+      adm[W.group].push_back({j, q});
       W.queue.pop_front();
       W.busy = true;
       G.slot_job[q] = j;
@@ -1185,8 +1261,14 @@ int serve_impl(bm_ctx* c, const bm_dataset* ds, int nds, const bm_job* jobs, int
       G.running += 1;
       running += 1;
       inflight += bytes;
-      res[j].admitted = elapsed();
       ++admitted;
+    }
+    for (size_t gi = 0; gi < st.groups.size(); ++gi) {
+      if (adm[gi].empty()) continue;
+      ServeGroup& G = st.groups[gi];
+      BM_TRY(serve_admit(c, st, workers, job_worker, G, adm[gi], ds[G.d], jobs, sp));
+      const double t = elapsed();
+      for (const auto& jq : adm[gi]) res[jq.first].admitted = t;
     }
     peak_running = std::max(peak_running, running);
     peak_bytes = std::max(peak_bytes, inflight);

@@ -150,6 +150,7 @@ struct KppArgs {
   uint64_t g;            // global pass index of the draws (when gs is null)
   const uint64_t* gs;    // [job] global pass index per job (persistent rounds), or null
   int32_t n_cand;
+  const int32_t* job_slot;  // nullable: launch job j works on job index job_slot[j]
 };
 // Persistent round kernel: every worker runs its (optional) re-evaluation
 // and passes_p passes of Algorithm 1 on its own group of workgroups.

@@ -710,7 +710,10 @@ __device__ __noinline__ void kpp_setup_job(const KppArgs& a, int job) {
   __syncthreads();
 }
 
-__global__ __launch_bounds__(kWG) void k_kpp_setup(KppArgs a) { kpp_setup_job(a, blockIdx.x); }
+// Job index of launch job j (a batch may cover any set of workspace slots).
+__device__ inline int kpp_job(const KppArgs& a, int j) { return a.job_slot ? a.job_slot[j] : j; }
+
+__global__ __launch_bounds__(kWG) void k_kpp_setup(KppArgs a) { kpp_setup_job(a, kpp_job(a, blockIdx.x)); }
 
 // D_i = min over kept centroids of ||S_i - c_j||^2 (slot 0) and the tile's sum.
 __device__ __noinline__ void kpp_init_tile(const KppArgs& a, int job, int64_t tile) {
@@ -734,7 +737,7 @@ __device__ __noinline__ void kpp_init_tile(const KppArgs& a, int job, int64_t ti
 }
 
 __global__ __launch_bounds__(kWG) void k_kpp_init(KppArgs a) {
-  kpp_init_tile(a, blockIdx.y, blockIdx.x);
+  kpp_init_tile(a, kpp_job(a, blockIdx.y), blockIdx.x);
 }
 
 // Wave-level monotone prefix over v[0..cnt): lane l sums a contiguous chunk
@@ -895,7 +898,7 @@ __device__ __noinline__ void kpp_step_job(const KppArgs& a, int job) {
   if (lane == 0) a.ks[job] = ks;
 }
 
-__global__ __launch_bounds__(64) void k_kpp_step(KppArgs a) { kpp_step_job(a, blockIdx.x); }
+__global__ __launch_bounds__(64) void k_kpp_step(KppArgs a) { kpp_step_job(a, kpp_job(a, blockIdx.x)); }
 
 // Potentials of the pending candidates: new D per candidate into the other
 // slots, with per-tile sums.
@@ -906,25 +909,76 @@ __device__ __noinline__ void kpp_pot_tile(const KppArgs& a, int job, int64_t til
   if (tile * kDTile >= s) return;
   const int64_t i = tile * kDTile + threadIdx.x;
   const float* S = a.S + job * a.S_stride;
-  __shared__ double red[4];
+  const int n = a.n, nc = ks.ncand;
+  // the candidates' rows in LDS; every point's row is read once for all of them
+  extern __shared__ float cand_rows[];  // [3][n]
+  for (int e = threadIdx.x; e < nc * n; e += kWG) {
+    const int c = e / n, d = e - c * n;
+    cand_rows[e] = S[(int64_t)ks.cand[c] * a.ld + d];
+  }
+  __syncthreads();
+  __shared__ double red[12];
   float dcur = 0.f;
   if (i < s && ks.has_d) dcur = a.D[(int64_t)ks.dcur * a.D_slot_stride + job * a.D_job_stride + i];
-  for (int c = 0; c < ks.ncand; ++c) {
-    const float* xc = S + (int64_t)ks.cand[c] * a.ld;
-    float m = 0.f;
-    if (i < s) {
-      const float dc = dist_direct_mem(S + i * a.ld, xc, a.n);
-      m = ks.has_d ? min_nan(dcur, dc) : dc;
-      a.D[(int64_t)other_slot(ks.dcur, c) * a.D_slot_stride + job * a.D_job_stride + i] = m;
+  // direct-form distances with the operation order of dist_direct_mem
+  float p[3][4] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+  if (i < s) {
+    const float* x = S + i * a.ld;
+    const int n4 = n & ~3;
+    const bool vec = (a.ld % 4) == 0 && (((uintptr_t)S & 15) == 0);
+    for (int d = 0; d < n4; d += 4) {
+      float4 xv;
+      if (vec) {
+        xv = *reinterpret_cast<const float4*>(x + d);
+      } else {
+        xv = make_float4(x[d], x[d + 1], x[d + 2], x[d + 3]);
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (c < nc) {
+          const float* cr = cand_rows + c * n + d;
+          const float t0 = xv.x - cr[0], t1 = xv.y - cr[1], t2 = xv.z - cr[2], t3 = xv.w - cr[3];
+          p[c][0] = fmaf(t0, t0, p[c][0]);
+          p[c][1] = fmaf(t1, t1, p[c][1]);
+          p[c][2] = fmaf(t2, t2, p[c][2]);
+          p[c][3] = fmaf(t3, t3, p[c][3]);
+        }
+      }
     }
-    const double ts = block_sum_f64(i < s ? (double)m : 0.0, red);
-    if (threadIdx.x == 0)
-      a.Dt[((int64_t)other_slot(ks.dcur, c) * a.njobs + job) * a.ndt_max + tile] = ts;
+    for (int d = n4; d < n; ++d) {
+      const float xd = x[d];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (c < nc) {
+          const float t = xd - cand_rows[c * n + d];
+          p[c][0] = fmaf(t, t, p[c][0]);
+        }
+      }
+    }
   }
+  const int wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if (c < nc) {
+      float m = 0.f;
+      if (i < s) {
+        const float dc = (p[c][0] + p[c][1]) + (p[c][2] + p[c][3]);
+        m = ks.has_d ? min_nan(dcur, dc) : dc;
+        a.D[(int64_t)other_slot(ks.dcur, c) * a.D_slot_stride + job * a.D_job_stride + i] = m;
+      }
+      const double part = wave_sum_f64(i < s ? (double)m : 0.0);
+      if ((threadIdx.x & 63) == 0) red[c * 4 + wv] = part;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int c = 0; c < nc; ++c)
+      a.Dt[((int64_t)other_slot(ks.dcur, c) * a.njobs + job) * a.ndt_max + tile] =
+          (red[c * 4] + red[c * 4 + 1]) + (red[c * 4 + 2] + red[c * 4 + 3]);
 }
 
 __global__ __launch_bounds__(kWG) void k_kpp_pot(KppArgs a) {
-  kpp_pot_tile(a, blockIdx.y, blockIdx.x);
+  kpp_pot_tile(a, kpp_job(a, blockIdx.y), blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1659,7 +1713,13 @@ hipError_t launch_kpp_step(hipStream_t st, const KppArgs& a, int32_t njobs) {
 
 hipError_t launch_kpp_pot(hipStream_t st, const KppArgs& a, int32_t njobs, int64_t max_s) {
   const dim3 grid((unsigned)((max_s + kDTile - 1) / kDTile), (unsigned)njobs);
-  hipLaunchKernelGGL(k_kpp_pot, grid, dim3(kWG), 0, st, a);
+  const size_t lds = (size_t)3 * a.n * sizeof(float);  // candidate rows
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_kpp_pot,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_kpp_pot, grid, dim3(kWG), lds, st, a);
   return hipGetLastError();
 }
 

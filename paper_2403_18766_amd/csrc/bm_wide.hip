@@ -14,8 +14,9 @@
 // argmin then follows the same rules as the narrow path: e_j = ||c_j||^2 -
 // 2 x.c_j, a rigorous bound on its FP32 rounding error (any summation order
 // of cp terms), a direct-form re-decision of every point whose best two e are
-// closer than that bound, lowest index on ties, and the winner's distance in
-// the direct form sum_d (x_d - c_d)^2 (four partial sums by d mod 4).
+// closer than that bound (the whole wave evaluates one such point's centres
+// together), lowest index on ties, and the winner's distance in the direct
+// form sum_d (x_d - c_d)^2 (four partial sums by d mod 4).
 //
 // Lloyd labels ping-pong between two arrays (assignment q writes array q mod
 // 2), so the update kernel sees the old and the new label of every point.
@@ -238,27 +239,43 @@ __global__ __launch_bounds__(256, 2) void k_assign_wide(AssignArgs a) {
     const bool valid = tid < np;
     double fpart = 0.0;
     int near = 0;
-    if (valid) {
-      const float* x = S + i * (int64_t)ld;
-      const float B = kB * (sqrtf(xx) * cmax + cmax2);
-      const bool recheck = !((pe2 - pe1) > 2.f * B + 2.5e-5f * fabsf(pe2 + xx));
-      int jw = pj1;
-      if (recheck) {
-        float b1 = __builtin_inff(), b2 = __builtin_inff();
-        int jb = 0;
-        for (int j = 0; j < k; ++j) {
-          const float dd = dist_wide(x, C + (int64_t)j * cp, n, vec);
-          if (dd < b1) {
-            b2 = b1;
-            b1 = dd;
-            jb = j;
-          } else if (dd < b2) {
-            b2 = dd;
-          }
+    const float* x = S + i * (int64_t)ld;
+    const float B = kB * (sqrtf(xx) * cmax + cmax2);
+    const bool recheck = valid && !((pe2 - pe1) > 2.f * B + 2.5e-5f * fabsf(pe2 + xx));
+    int jw = pj1;
+    // direct-form re-decision, one flagged point at a time by the whole wave:
+    // lane l takes the centres l, l + 64, ... in order, then the best and
+    // second best merge across lanes (lowest index on equal distances)
+    unsigned long long pending = __ballot(recheck);
+    while (pending) {
+      const int src = __ffsll(pending) - 1;
+      pending &= pending - 1;
+      const float* xs = S + (cb + wv * 64 + src) * (int64_t)ld;
+      float b1 = __builtin_inff(), b2 = __builtin_inff();
+      int jb = 0;
+      for (int j = lane; j < k; j += 64) {
+        const float dd = dist_wide(xs, C + (int64_t)j * cp, n, vec);
+        if (dd < b1) {
+          b2 = b1;
+          b1 = dd;
+          jb = j;
+        } else if (dd < b2) {
+          b2 = dd;
         }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const float o1 = __shfl_xor(b1, off, 64);
+        const int oj = __shfl_xor(jb, off, 64);
+        const float o2 = __shfl_xor(b2, off, 64);
+        top2_merge(b1, jb, b2, o1, oj, o2);
+      }
+      if (lane == src) {
         jw = jb;
         if (b2 - b1 < 1e-5f * b2) near = 1;
       }
+    }
+    if (valid) {
       fpart = (double)dist_wide(x, C + (int64_t)jw * cp, n, vec);
       if (lab) lab[i] = jw;
     }
