@@ -93,6 +93,45 @@ def calibrate_copy(torch, dev, mib=512):
     log(f"copy calibration: 3 x {mib} MiB read + {mib} MiB written")
 
 
+SERVE = dict(m=4_000_000, dims=(16, 64, 256), ks=(10, 50, 200), s_min=1024, s_max=262144,
+             workers=32, rate=2000.0, budget_gb=200)
+
+
+def serve_run(torch, dev, njobs):
+    """The serving workload: Poisson arrivals of single-pass jobs against three
+    resident data sets; returns the latency summary."""
+    import numpy as np
+
+    from paper_2403_18766_amd import api, datagen
+    log("generating serving data sets")
+    Xs = [torch.from_numpy(datagen.serving_dataset(n, m=SERVE["m"])).to(dev) for n in SERVE["dims"]]
+    r = np.random.default_rng(0)
+    t = 0.0
+    jobs = []
+    ls, lb = math.log(SERVE["s_min"]), math.log(SERVE["s_max"] + 1)
+    for _ in range(njobs):
+        t += float(r.exponential(1.0 / SERVE["rate"]))
+        s = min(SERVE["s_max"], int(math.floor(math.exp(r.uniform(ls, lb)))))
+        jobs.append(dict(arrival=t, s=s, dataset=int(r.integers(len(Xs))),
+                         k=int(SERVE["ks"][r.integers(len(SERVE["ks"]))]),
+                         worker=int(r.integers(SERVE["workers"]))))
+    log("serving", njobs, "jobs")
+    res, st = api.serve(Xs, jobs, seed=0, budget_bytes=SERVE["budget_gb"] << 30, max_slots=64,
+                        paced=True)
+    lat = np.array([x["finished"] - j["arrival"] for x, j in zip(res, jobs)]) * 1e3
+    del Xs
+    torch.cuda.empty_cache()
+    return {"workload": (f"3 resident data sets of {SERVE['m']:,} points (noisy Gaussian mixtures, "
+                         f"n = 16, 64, 256); {njobs} jobs, Poisson arrivals at "
+                         f"{SERVE['rate']:.0f}/s; k in (10, 50, 200); s log-uniform in "
+                         f"[{SERVE['s_min']}, {SERVE['s_max']}]; 32 workers per (data set, k); "
+                         f"{SERVE['budget_gb']} GiB budget"),
+            "jobs_per_s": njobs / st["seconds"], "p50_latency_ms": float(np.percentile(lat, 50)),
+            "p99_latency_ms": float(np.percentile(lat, 99)), "wall_s": st["seconds"],
+            "lloyd_steps": st["steps"], "peak_running": st["peak_running"],
+            "peak_bytes": st["peak_bytes"]}
+
+
 def reference_f(X):
     from paper_2403_18766_amd import datagen
     path = os.path.join(ROOT, "tests", "golden", f"{WORKLOAD['name']}_reference.json")
@@ -115,6 +154,8 @@ def main():
     ap.add_argument("--cpu-workers", type=int, default=32)
     ap.add_argument("--cpu-passes", type=int, default=10)
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-target run")
+    ap.add_argument("--serve-jobs", type=int, default=2000,
+                    help="jobs of the serving measurement (0 skips it)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed steps, copy 512 MiB three times (counter scaling)")
     ap.add_argument("--mode", type=int, default=1,
@@ -194,6 +235,8 @@ def main():
                 break
 
     cpu = None if args.no_cpu else cpu_baseline(X, args.cpu_workers, args.cpu_passes)
+    del Xd
+    serving = serve_run(torch, dev, args.serve_jobs) if args.serve_jobs > 0 else None
     f_full = results[-1]["f_full"]
     out = {
         "metric": METRIC, "value": value, "unit": "dists/s", "n_gpus": 1, "steps": args.steps,
@@ -213,7 +256,8 @@ def main():
         "f_oracle": f_ref,
         "f_gap_vs_oracle": (f_full - f_ref) / f_ref if f_ref else None,
         "time_to_target": ttt,
-        "p99_latency_ms": None,
+        "p99_latency_ms": serving["p99_latency_ms"] if serving else None,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 
