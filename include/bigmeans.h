@@ -79,8 +79,12 @@ typedef enum bm_size_policy {
   BM_SIZE_UNIFORM = 0,    /* s uniform integer in [s_min, s_max] (Algorithm 1) */
   BM_SIZE_FIXED = 1,      /* s = s_min (s_min == s_max) */
   BM_SIZE_LOGUNIFORM = 2, /* floor(exp(ln a + u (ln(b+1) - ln a))), clamped to [a, b] */
-  BM_SIZE_BINS = 3        /* round 0 log-uniform; later rounds pick one of 5 log-width bins
+  BM_SIZE_BINS = 3,       /* round 0 log-uniform; later rounds pick one of 5 log-width bins
                              with weight (acc_i + 1)/(passes_i + 2), then log-uniform inside */
+  BM_SIZE_SHRINK = 4      /* exploration narrowing to exploitation (Section 7, future work):
+                             round 0, or while L is empty, log-uniform; round t log-uniform in
+                             [mu / r_t, mu r_t] clamped to [a, b + 1), mu = round-half-up mean
+                             of L over earlier rounds, ln r_t = (ln(b+1) - ln a) / 2 * 2^-t */
 } bm_size_policy;
 
 typedef enum bm_purpose {
@@ -330,11 +334,12 @@ BM_API int bm_get_stats(bm_ctx* ctx, bm_stats* out);
 
 /* Host-only: the sample size of `worker` in round t under params' policy,
  * given the BINS statistics so far (bin_acc/bin_passes: 5 counts each, may
- * be NULL for other policies).  Writes the size and its bin (0..4).  Needs no
- * device. */
+ * be NULL for other policies) and the list L of earlier rounds (l_sum, l_count:
+ * sum and number of its sizes; SHRINK).  Writes the size and its bin (0..4).
+ * Needs no device. */
 BM_API int bm_draw_size(const bm_params* params, uint32_t worker, int32_t t,
-                        const int64_t* bin_acc, const int64_t* bin_passes,
-                        int64_t* s_out, int32_t* bin_out);
+                        const int64_t* bin_acc, const int64_t* bin_passes, int64_t l_sum,
+                        int64_t l_count, int64_t* s_out, int32_t* bin_out);
 
 /* Host-only: Philox4x64-10 block B(ctr, key) -> out[4].  Needs no device. */
 BM_API void bm_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);

@@ -30,6 +30,11 @@ Size policies (the paper draws s_w uniformly in [s_min, s_max]):
               bins of ln s with probability proportional to (a_i + 1)/(n_i + 2)
               (a_i acceptances and n_i passes seen in bin i so far), then draw
               log-uniformly inside the bin.
+  SHRINK      (the exploration-then-exploitation the paper leaves to future
+              work, Section 7) round 0, or while L is empty, as LOGUNIFORM;
+              later rounds draw log-uniformly in [mu / r_t, mu r_t] clamped to
+              [a, b + 1), where mu is the round-half-up mean of L over earlier
+              rounds and ln r_t = (ln(b + 1) - ln a) / 2 * 2^-t.
 with w = B((t, 0, 0, 0), key(seed, worker, SIZE)).
 """
 
@@ -40,7 +45,7 @@ import numpy as np
 
 from . import kmeans, rng
 
-SIZE_UNIFORM, SIZE_FIXED, SIZE_LOGUNIFORM, SIZE_BINS = 0, 1, 2, 3
+SIZE_UNIFORM, SIZE_FIXED, SIZE_LOGUNIFORM, SIZE_BINS, SIZE_SHRINK = 0, 1, 2, 3, 4
 N_BINS = 5
 
 
@@ -69,8 +74,10 @@ def _log_edges(a, b):
     return la, (math.log(b + 1) - la)
 
 
-def draw_size(params, worker, t, bin_stats):
-    """Sample size of `worker` for round t, and the bin (0..4) it falls in."""
+def draw_size(params, worker, t, bin_stats, l_stats=None):
+    """Sample size of `worker` for round t, and the bin (0..4) it falls in.
+    bin_stats: BINS statistics of earlier rounds; l_stats: (sum, count) of
+    the list L over earlier rounds (SHRINK)."""
     a, b = int(params.s_min), int(params.s_max)
     w = rng.philox_block_scalar((t, 0, 0, 0),
                                 rng.stream_key(params.seed, worker, rng.PURPOSE_SIZE))
@@ -80,7 +87,17 @@ def draw_size(params, worker, t, bin_stats):
     if pol == SIZE_FIXED:
         return a, 0
     la, width = _log_edges(a, b)
-    if pol == SIZE_LOGUNIFORM or (pol == SIZE_BINS and t == 0):
+    if pol == SIZE_SHRINK and t > 0 and l_stats is not None and l_stats[1] > 0:
+        l_sum, l_count = l_stats
+        mu = (l_sum + l_count // 2) // l_count
+        lm = math.log(mu)
+        half = math.ldexp(width / 2.0, -t)
+        lo = max(la, lm - half)
+        hi = min(la + width, lm + half)
+        v = lo + rng.u01(w[0]) * (hi - lo)
+        s = int(math.floor(math.exp(v)))
+        return min(max(s, a), b), min(N_BINS - 1, int((v - la) / width * N_BINS))
+    if pol in (SIZE_LOGUNIFORM, SIZE_SHRINK) or (pol == SIZE_BINS and t == 0):
         u = rng.u01(w[0])
         s = int(math.floor(math.exp(la + u * width)))
         return min(max(s, a), b), min(N_BINS - 1, int(u * N_BINS))
@@ -153,8 +170,9 @@ def bigmeans_run(X, params, keep_trace=False):
     for t in range(P.rounds_T):
         round_acc = [0] * N_BINS
         round_passes = [0] * N_BINS
+        l_stats = (sum(e[3] for e in L), len(L))   # L over earlier rounds
         for w in range(W):
-            s_new, b = draw_size(P, w, t, bin_stats)
+            s_new, b = draw_size(P, w, t, bin_stats, l_stats)
             for q in range(P.passes_p):
                 # the re-evaluation after a size change happens before the first pass
                 res = worker_pass(X, C[w], deg[w], fhat[w], s_cur[w], s_new, P.seed, w,

@@ -12,7 +12,7 @@ LIB_PATH = os.path.join(HERE, "libbigmeans.so")
 
 BM_OK, BM_E_ARG, BM_E_NOMEM, BM_E_HIP, BM_E_NONFINITE, BM_E_STATE = 0, -1, -2, -3, -4, -5
 BM_FP32, BM_BF16 = 0, 1
-BM_SIZE_UNIFORM, BM_SIZE_FIXED, BM_SIZE_LOGUNIFORM, BM_SIZE_BINS = 0, 1, 2, 3
+BM_SIZE_UNIFORM, BM_SIZE_FIXED, BM_SIZE_LOGUNIFORM, BM_SIZE_BINS, BM_SIZE_SHRINK = 0, 1, 2, 3, 4
 BM_PURPOSE_SIZE, BM_PURPOSE_SAMPLE, BM_PURPOSE_KMPP, BM_PURPOSE_RECALC, BM_PURPOSE_FINAL = 1, 2, 3, 4, 5
 BM_FINAL_WORKER = 0xFFFFFF
 
@@ -93,8 +93,8 @@ SIGNATURES = [
     ("bm_bigmeans_run", ct.c_int, [ct.c_void_p, ct.c_void_p, ct.POINTER(Params), ct.c_void_p,
                                    ct.c_void_p, ct.POINTER(Result), TRACE_CB, ct.c_void_p]),
     ("bm_draw_size", ct.c_int, [ct.POINTER(Params), ct.c_uint32, ct.c_int32,
-                                ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int64),
-                                ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int32)]),
+                                ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int64), ct.c_int64,
+                                ct.c_int64, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int32)]),
     ("bm_serve", ct.c_int, [ct.c_void_p, ct.POINTER(Dataset), ct.c_int32, ct.POINTER(Job),
                             ct.c_int32, ct.POINTER(ServeParams), ct.POINTER(JobResult),
                             ct.POINTER(ServeStats)]),

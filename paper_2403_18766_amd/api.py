@@ -227,7 +227,7 @@ def get_stats(device):
     return {f: getattr(st, f) for f, _ in _lib.Stats._fields_}
 
 
-def draw_size(params, m, n, worker, t, bin_acc=None, bin_passes=None):
+def draw_size(params, m, n, worker, t, bin_acc=None, bin_passes=None, l_sum=0, l_count=0):
     """bm_draw_size (host only): the sample size of `worker` in round t and its bin."""
     lib = _lib.load()
     cp = params.c_struct(m, n)
@@ -236,7 +236,8 @@ def draw_size(params, m, n, worker, t, bin_acc=None, bin_passes=None):
     bp = arr(*(bin_passes or [0] * 5))
     s = ct.c_int64()
     b = ct.c_int32()
-    rc = lib.bm_draw_size(ct.byref(cp), int(worker), int(t), ba, bp, ct.byref(s), ct.byref(b))
+    rc = lib.bm_draw_size(ct.byref(cp), int(worker), int(t), ba, bp, int(l_sum), int(l_count),
+                          ct.byref(s), ct.byref(b))
     if rc != 0:
         raise BigmeansError(rc, "bm_draw_size failed")
     return s.value, b.value

@@ -892,7 +892,7 @@ void round_keys(uint64_t m, uint64_t seed, uint32_t worker, uint32_t purpose, ui
 
 // Sample-size draw of Algorithm 1 under the configured policy.
 int64_t draw_size(const bm_params& p, uint32_t worker, int t, const int64_t* bacc,
-                  const int64_t* bpass, int32_t* bin) {
+                  const int64_t* bpass, int64_t l_sum, int64_t l_count, int32_t* bin) {
   uint64_t k0, k1;
   bm::stream_key(p.seed, worker, BM_PURPOSE_SIZE, &k0, &k1);
   const bm::U64x4 w = bm::philox_ctr((uint64_t)t, 0, 0, 0, k0, k1);
@@ -902,7 +902,19 @@ int64_t draw_size(const bm_params& p, uint32_t worker, int t, const int64_t* bac
   if (p.size_policy == BM_SIZE_FIXED) return a;
   const double la = std::log((double)a);
   const double width = std::log((double)(b + 1)) - la;
-  if (p.size_policy == BM_SIZE_LOGUNIFORM || t == 0) {
+  if (p.size_policy == BM_SIZE_SHRINK && t > 0 && l_count > 0) {
+    // log-uniform in [mu / r_t, mu r_t] around the mean of L, ln r_t = width / 2 * 2^-t
+    const int64_t mu = (l_sum + l_count / 2) / l_count;
+    const double lm = std::log((double)mu);
+    const double half = std::ldexp(width / 2.0, -t);
+    const double lo = std::max(la, lm - half);
+    const double hi = std::min(la + width, lm + half);
+    const double v = lo + bm::u01(w.w[0]) * (hi - lo);
+    const int64_t s = (int64_t)std::floor(std::exp(v));
+    *bin = std::min(kNBins - 1, (int)((v - la) / width * kNBins));
+    return std::min(std::max(s, a), b);
+  }
+  if (p.size_policy == BM_SIZE_LOGUNIFORM || p.size_policy == BM_SIZE_SHRINK || t == 0) {
     const double u = bm::u01(w.w[0]);
     int64_t s = (int64_t)std::floor(std::exp(la + u * width));
     *bin = std::min(kNBins - 1, (int)(u * kNBins));
@@ -940,7 +952,7 @@ int validate_params(bm_ctx* c, const bm_params* p) {
     return c->fail(BM_E_ARG, "need workers >= 1, rounds_T >= 0, passes_p >= 1");
   if (p->max_iter < 0 || !(p->tol >= 0.0)) return c->fail(BM_E_ARG, "need max_iter >= 0, tol >= 0");
   if (p->n_candidates < 1 || p->n_candidates > 3) return c->fail(BM_E_ARG, "n_candidates in 1..3");
-  if (p->size_policy < 0 || p->size_policy > 3) return c->fail(BM_E_ARG, "unknown size policy");
+  if (p->size_policy < 0 || p->size_policy > BM_SIZE_SHRINK) return c->fail(BM_E_ARG, "unknown size policy");
   if (p->size_policy == BM_SIZE_FIXED && p->s_min != p->s_max)
     return c->fail(BM_E_ARG, "FIXED size policy needs s_min == s_max");
   BM_TRY(check_prec(c, p->prec));
@@ -1545,12 +1557,15 @@ BM_API int bm_objective(bm_ctx* c, const float* X, int64_t m, int32_t n, const f
 }
 
 BM_API int bm_draw_size(const bm_params* params, uint32_t worker, int32_t t, const int64_t* bin_acc,
-                        const int64_t* bin_passes, int64_t* s_out, int32_t* bin_out) {
+                        const int64_t* bin_passes, int64_t l_sum, int64_t l_count, int64_t* s_out,
+                        int32_t* bin_out) {
   if (!params || !s_out || t < 0) return BM_E_ARG;
+  if (params->size_policy < 0 || params->size_policy > BM_SIZE_SHRINK) return BM_E_ARG;
   if (params->size_policy == BM_SIZE_BINS && t > 0 && (!bin_acc || !bin_passes)) return BM_E_ARG;
   if (params->s_min < 1 || params->s_min > params->s_max) return BM_E_ARG;
+  if (l_count < 0 || l_sum < 0) return BM_E_ARG;
   int32_t bin = 0;
-  *s_out = draw_size(*params, worker, t, bin_acc, bin_passes, &bin);
+  *s_out = draw_size(*params, worker, t, bin_acc, bin_passes, l_sum, l_count, &bin);
   if (bin_out) *bin_out = bin;
   return BM_OK;
 }
@@ -1660,7 +1675,8 @@ BM_API int bm_bigmeans_run(bm_ctx* c, const float* X, const bm_params* params, f
 
   for (int t = 0; t < p.rounds_T; ++t) {
     int64_t rpass[kNBins] = {0}, racc[kNBins] = {0};
-    for (int w = 0; w < W; ++w) s_new[w] = draw_size(p, (uint32_t)w, t, bacc, bpass, &bin_cur[w]);
+    for (int w = 0; w < W; ++w)
+      s_new[w] = draw_size(p, (uint32_t)w, t, bacc, bpass, Lsum, Lcount, &bin_cur[w]);
 
     // persistent round: re-evaluations and all passes of all workers in one
     // launch (the multi-launch path below runs when it does not fit the device)

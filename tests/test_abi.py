@@ -71,7 +71,7 @@ def test_philox_block_matches_oracle(lib):
 
 
 @pytest.mark.parametrize("policy", [obm.SIZE_UNIFORM, obm.SIZE_FIXED, obm.SIZE_LOGUNIFORM,
-                                    obm.SIZE_BINS])
+                                    obm.SIZE_BINS, obm.SIZE_SHRINK])
 def test_size_draws_match_oracle(lib, policy):
     from paper_2403_18766_amd import api
     rr = np.random.default_rng(policy)
@@ -85,9 +85,11 @@ def test_size_draws_match_oracle(lib, policy):
             acc = [int(v) for v in rr.integers(0, 20, size=5)]
             passes = [x + int(v) for x, v in zip(acc, rr.integers(0, 20, size=5))]
             stats = {"acc": acc, "passes": passes}
+            cnt = int(rr.integers(0, 6))
+            lsum = int(sum(rr.integers(a, b + 1, size=cnt))) if cnt else 0
             for w in (0, 1, 7, 63):
-                want = obm.draw_size(op, w, t, stats)
-                got = api.draw_size(gp, 10**7, 4, w, t, acc, passes)
+                want = obm.draw_size(op, w, t, stats, (lsum, cnt))
+                got = api.draw_size(gp, 10**7, 4, w, t, acc, passes, lsum, cnt)
                 assert got == want, (a, b, t, w)
 
 
@@ -97,7 +99,12 @@ def test_draw_size_rejects_bad_arguments(lib):
                     max_iter=1, n_candidates=1, size_policy=0, prec=0, batched=1, tol=0.0, seed=0)
     s = ct.c_int64()
     b = ct.c_int32()
-    assert lib.bm_draw_size(ct.byref(p), 0, 0, None, None, ct.byref(s), ct.byref(b)) == _lib.BM_E_ARG
+    assert lib.bm_draw_size(ct.byref(p), 0, 0, None, None, 0, 0, ct.byref(s), ct.byref(b)) == _lib.BM_E_ARG
+    p.s_max = 100
+    p.size_policy = 5
+    assert lib.bm_draw_size(ct.byref(p), 0, 0, None, None, 0, 0, ct.byref(s), ct.byref(b)) == _lib.BM_E_ARG
+    p.size_policy = 4
+    assert lib.bm_draw_size(ct.byref(p), 0, 1, None, None, 10, -1, ct.byref(s), ct.byref(b)) == _lib.BM_E_ARG
 
 
 def test_create_without_gpu_reports_state_error(lib):

@@ -372,7 +372,7 @@ def test_bigmeans_uniform_sizes_matches_oracle(dev, api):
     assert g["improvements"] >= P["workers"]
 
 
-@pytest.mark.parametrize("policy,seed", [(2, 11), (0, 12), (3, 13)])
+@pytest.mark.parametrize("policy,seed", [(2, 11), (0, 12), (3, 13), (4, 14)])
 def test_bigmeans_execution_modes_identical(dev, api, policy, seed):
     # persistent rounds (1), one launch per Lloyd step (2) and one worker per
     # launch (0) compute the same arithmetic: results are bitwise identical
@@ -388,6 +388,18 @@ def test_bigmeans_execution_modes_identical(dev, api, policy, seed):
         assert a["improvements"] == b["improvements"]
         assert np.array_equal(a["C_best"].cpu().numpy(), b["C_best"].cpu().numpy())
         assert np.array_equal(a["Y"].cpu().numpy(), b["Y"].cpu().numpy())
+
+
+def test_bigmeans_shrink_policy_matches_oracle(dev, api):
+    # sizes narrowing around the mean of L (Section 7's open question)
+    X = _data("aniso28", 100_000, 3)
+    P = dict(k=25, workers=6, rounds_T=4, passes_p=4, s_min=2000, s_max=16000, seed=6,
+             size_policy=4)
+    say("bigmeans shrink", X.shape, P)
+    g = api.bigmeans_run(to_dev(X, dev), api.RunParams(**P))
+    o = obm.bigmeans_run(X, obm.Params(**P))
+    assert abs(g["f_full"] - o["f_full"]) <= 0.01 * o["f_full"]
+    assert 2000 <= g["s_opt"] <= 16000
 
 
 def test_bigmeans_bins_policy_runs(dev, api):

@@ -119,6 +119,32 @@ def test_bins_follow_improvement_statistics():
         assert edges[b] <= s <= edges[b + 1]
 
 
+def test_shrink_policy_narrows_around_mean_of_L():
+    # Section 7 leaves the choice of sizes beyond uniform draws open; SHRINK draws
+    # log-uniformly around the mean of L with a log-width halving every round
+    a, b = 4096, 131072
+    P = bigmeans.Params(k=2, workers=1, rounds_T=1, s_min=a, s_max=b,
+                        size_policy=bigmeans.SIZE_SHRINK, seed=3)
+    PL = bigmeans.Params(k=2, workers=1, rounds_T=1, s_min=a, s_max=b,
+                         size_policy=bigmeans.SIZE_LOGUNIFORM, seed=3)
+    # round 0 and an empty L: the log-uniform draw itself
+    for w in range(5):
+        assert bigmeans.draw_size(P, w, 0, None, (5000, 1)) == bigmeans.draw_size(PL, w, 0, None)
+        assert bigmeans.draw_size(P, w, 4, None, (0, 0)) == bigmeans.draw_size(PL, w, 4, None)
+    width = math.log(b + 1) - math.log(a)
+    for mu in (4096, 20000, 131072):
+        for t in range(1, 12):
+            r = math.exp(width / 2 * 2.0 ** -t)
+            lo, hi = max(a, mu / r), min(b + 1, mu * r)
+            sizes = [bigmeans.draw_size(P, w, t, None, (3 * mu, 3))[0] for w in range(200)]
+            assert all(math.floor(lo) <= s <= min(b, math.ceil(hi)) for s in sizes), (mu, t)
+            if t >= 8:   # late rounds: within 1% of the mean (clamped to the range)
+                assert all(abs(s - min(max(mu, a), b)) <= 0.01 * mu + 1 for s in sizes)
+    # with a vanishing range the draw is the mean of L up to the floor of exp(ln mu)
+    s1 = bigmeans.draw_size(P, 0, 30, None, (4097 + 4098, 2))[0]
+    assert 4097 <= s1 <= 4098
+
+
 def test_uniform_size_matches_contract():
     P = bigmeans.Params(k=2, workers=1, rounds_T=1, s_min=1000, s_max=4000, seed=9)
     w = rng.philox_block_scalar((3, 0, 0, 0), rng.stream_key(9, 2, rng.PURPOSE_SIZE))
