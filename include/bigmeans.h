@@ -73,6 +73,15 @@ typedef enum bm_status {
   BM_E_STATE = -5      /* context not usable (no device, destroyed workspace) */
 } bm_status;
 
+/* Arithmetic of the distance products on the matrix-core path (padded
+ * dimension above 64; narrower points use FP32 vector arithmetic whatever the
+ * precision).  BM_FP32: FP32 matrix cores.  BM_BF16: BF16 matrix cores with
+ * FP32 accumulation; every FP32 coordinate is split into a BF16 high part
+ * and a BF16 residual, and x.c is taken as xh.ch + xh.cl + xl.ch.  In both,
+ * a point whose two best centres are closer than the rigorous error bound of
+ * that arithmetic is re-decided with FP32 direct-form distances of the FP32
+ * rows, and every winner's distance (hence f) is the FP32 direct form, so
+ * labels and f agree with the FP32 path except at such near ties. */
 typedef enum bm_precision { BM_FP32 = 0, BM_BF16 = 1 } bm_precision;
 
 typedef enum bm_size_policy {
@@ -161,7 +170,7 @@ BM_API int bm_seed(bm_ctx* ctx, const float* S, int64_t s, int32_t n, int32_t k,
  *   degenerate_out device, k uint8 (or NULL): 1 if cluster j is empty under
  *                  the final assignment.
  *   labels_out     device, s int32 (or NULL): final labels.
- * prec must be BM_FP32.  Returns BM_E_NONFINITE if f is not finite.
+ * prec: bm_precision.  Returns BM_E_NONFINITE if f is not finite.
  * Synchronises the stream. */
 BM_API int bm_lloyd(bm_ctx* ctx, const float* S, int64_t s, int32_t n, int32_t k, float* C,
                     int32_t max_iter, double tol, int32_t prec, double* f_out,
@@ -174,7 +183,7 @@ BM_API int bm_lloyd(bm_ctx* ctx, const float* S, int64_t s, int32_t n, int32_t k
  *   labels_out    device, m int32, or NULL.
  *   near_ties_out host, or NULL: number of points whose two smallest squared
  *                 distances d1 <= d2 satisfy d2 - d1 < 1e-5 d2.
- * prec must be BM_FP32.  Returns BM_E_NONFINITE if f is not finite.
+ * prec: bm_precision.  Returns BM_E_NONFINITE if f is not finite.
  * Synchronises the stream. */
 BM_API int bm_objective(bm_ctx* ctx, const float* X, int64_t m, int32_t n, const float* C,
                         int32_t k, int32_t prec, double* f_out, int32_t* labels_out,
@@ -193,7 +202,7 @@ typedef struct bm_params {
   int32_t max_iter;    /* Lloyd update cap (Section 5: 300) */
   int32_t n_candidates;/* K-means++ candidates (Section 5: 3) */
   int32_t size_policy; /* bm_size_policy */
-  int32_t prec;        /* BM_FP32 */
+  int32_t prec;        /* bm_precision of the Lloyd and objective distances */
   int32_t batched;     /* 1: one persistent cooperative launch per round, each worker on
                              its own group of workgroups inside one XCD (default; wide
                              points, or a device placement that cannot hold every
@@ -270,7 +279,8 @@ typedef struct bm_job {
   int32_t dataset; /* index into the dataset array */
   int32_t k;
   int32_t worker;
-  int32_t prec;    /* BM_FP32 */
+  int32_t prec;    /* bm_precision (jobs of one data set and k run in one launch per
+                      precision) */
 } bm_job;
 
 typedef struct bm_job_result {

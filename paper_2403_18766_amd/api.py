@@ -14,7 +14,7 @@ from dataclasses import dataclass
 import torch
 
 from . import _lib
-from ._lib import (BM_FP32, BM_PURPOSE_SAMPLE, BM_SIZE_UNIFORM, BM_E_NONFINITE, Params as _CParams,
+from ._lib import (BM_BF16, BM_FP32, BM_PURPOSE_SAMPLE, BM_SIZE_UNIFORM, BM_E_NONFINITE, Params as _CParams,
                    Result as _CResult, STATUS_NAMES, TRACE_CB)
 
 
@@ -103,7 +103,7 @@ def seed(S, C, degenerate, n_candidates=3, seed=0, worker=0, g=0, return_picks=F
     return (C, deg, picks) if return_picks else (C, deg)
 
 
-def lloyd(S, C0, max_iter=300, tol=1e-4, labels=True):
+def lloyd(S, C0, max_iter=300, tol=1e-4, labels=True, prec=BM_FP32):
     """bm_lloyd from a copy of C0.  Returns a dict with C, f, iters, deg, labels."""
     _dev(S, torch.float32, "S", 2)
     s, n = S.shape
@@ -116,13 +116,13 @@ def lloyd(S, C0, max_iter=300, tol=1e-4, labels=True):
     f = ct.c_double()
     iters = ct.c_int32()
     lib, c = _ctx(S.device)
-    rc = lib.bm_lloyd(c, _ptr(S), s, n, k, _ptr(C), int(max_iter), float(tol), BM_FP32,
+    rc = lib.bm_lloyd(c, _ptr(S), s, n, k, _ptr(C), int(max_iter), float(tol), int(prec),
                       ct.byref(f), ct.byref(iters), _ptr(deg), _ptr(lab))
     _check(lib, c, rc, allow_nonfinite=True)
     return {"C": C, "f": f.value, "iters": iters.value, "deg": deg, "labels": lab}
 
 
-def objective(X, C, labels=True, near_ties=True):
+def objective(X, C, labels=True, near_ties=True, prec=BM_FP32):
     """bm_objective: (f, labels or None, near-tie count or None)."""
     _dev(X, torch.float32, "X", 2)
     _dev(C, torch.float32, "C", 2)
@@ -134,7 +134,7 @@ def objective(X, C, labels=True, near_ties=True):
     f = ct.c_double()
     near = ct.c_int64()
     lib, c = _ctx(X.device)
-    rc = lib.bm_objective(c, _ptr(X), m, n, _ptr(C), k, BM_FP32, ct.byref(f), _ptr(lab),
+    rc = lib.bm_objective(c, _ptr(X), m, n, _ptr(C), k, int(prec), ct.byref(f), _ptr(lab),
                           ct.byref(near) if near_ties else None)
     _check(lib, c, rc, allow_nonfinite=True)
     return f.value, lab, (near.value if near_ties else None)
@@ -155,13 +155,14 @@ class RunParams:
     size_policy: int = BM_SIZE_UNIFORM
     seed: int = 0
     batched: int = 1   # 1 persistent rounds, 2 one launch per Lloyd step, 0 one worker per launch
+    prec: int = BM_FP32  # BM_BF16: split-BF16 matrix-core distances for wide points
 
     def c_struct(self, m, n):
         return _CParams(m=int(m), s_min=int(self.s_min), s_max=int(self.s_max), n=int(n),
                         k=int(self.k), workers=int(self.workers), rounds_T=int(self.rounds_T),
                         passes_p=int(self.passes_p), max_iter=int(self.max_iter),
                         n_candidates=int(self.n_candidates), size_policy=int(self.size_policy),
-                        prec=BM_FP32, batched=int(self.batched), tol=float(self.tol),
+                        prec=int(self.prec), batched=int(self.batched), tol=float(self.tol),
                         seed=int(self.seed))
 
 
@@ -283,7 +284,7 @@ def serve(datasets, jobs, seed=0, budget_bytes=200 << 30, max_slots=64, max_iter
         jb[i].dataset = int(j["dataset"])
         jb[i].k = int(j["k"])
         jb[i].worker = int(j["worker"])
-        jb[i].prec = BM_FP32
+        jb[i].prec = int(j.get("prec", BM_FP32))
     sp = _lib.ServeParams(seed=seed, budget_bytes=int(budget_bytes), max_slots=max_slots,
                           max_iter=max_iter, n_candidates=n_candidates, paced=1 if paced else 0,
                           tol=tol)

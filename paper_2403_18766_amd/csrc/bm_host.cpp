@@ -27,6 +27,7 @@
 
 #include "../../include/bigmeans.h"
 #include "bm_internal.h"
+#include "bm_precision.h"
 #include "bm_rng.h"
 
 using bm::JobState;
@@ -325,6 +326,7 @@ struct LloydSetup {
   bm::AssignArgs a{};
   bm::FinalizeArgs f{};
   bool wide = false;
+  bool bf16 = false;  // wide points: dot products on the BF16 matrix cores (split operands)
   int32_t* lab[2] = {nullptr, nullptr};  // wide points: assignment q writes lab[q % 2]
   int64_t lab_stride = 0;
   JobState* js = nullptr;
@@ -335,7 +337,7 @@ struct LloydSetup {
 // Arguments for the slots first..first+J-1 (tile map set separately).  With
 // `accept`, a stopping job replaces the slot's incumbent on strict improvement.
 int lloyd_setup(bm_ctx* c, const BatchView& b, int max_iter, double tol, int32_t* labels,
-                int64_t lab_stride, bool accept, LloydSetup* L) {
+                int64_t lab_stride, bool accept, LloydSetup* L, int prec = BM_FP32) {
   const int J = b.njobs, first = b.first, k = b.k, cp = b.cp;
   if (!labels) {
     labels = P<int32_t>(c->labels) + (int64_t)first * c->max_s;
@@ -397,6 +399,7 @@ int lloyd_setup(bm_ctx* c, const BatchView& b, int max_iter, double tol, int32_t
   // labels to lab[q % 2] (lab[0] = labels, lab[1] = a second buffer with the
   // same layout); a separate kernel adds the label changes to the sums.
   L->wide = cp > bm::kMaxRegDim;
+  L->bf16 = L->wide && prec == BM_BF16;
   L->lab[0] = labels;
   L->lab[1] = nullptr;
   L->lab_stride = lab_stride;
@@ -425,7 +428,10 @@ int lloyd_launch(bm_ctx* c, LloydSetup& L, const BatchView& b, const TileMap& tm
   if (tm.total > c->tile_cap) return c->fail(BM_E_STATE, "tile map not uploaded");
   if (prof_slot >= 0) HIP_TRY(c, hipEventRecord(c->pev[2 * prof_slot], c->stream));
   if (L.wide) {
-    HIP_TRY(c, bm::launch_assign_wide(c->stream, L.a, tm.total, true));
+    if (L.bf16)
+      HIP_TRY(c, bm::launch_assign_wide_bf16(c->stream, L.a, tm.total, true));
+    else
+      HIP_TRY(c, bm::launch_assign_wide(c->stream, L.a, tm.total, true));
     HIP_TRY(c, bm::launch_update_wide(c->stream, b.S, b.S_stride, b.ld, b.n, b.cp, b.k, L.a.s, L.js,
                                       J, max_size, L.lab[0], L.lab[1], L.lab_stride, L.acc, L.cnt,
                                       L.a.scale));
@@ -445,10 +451,11 @@ int lloyd_launch(bm_ctx* c, LloydSetup& L, const BatchView& b, const TileMap& tm
 // js, degenerate flags in deg_work and the final labels in `labels` (or in
 // the workspace label buffer when labels is null).
 int lloyd_batch(bm_ctx* c, const BatchView& b, int max_iter, double tol, int32_t* labels,
-                int64_t lab_stride, bool accept = false, std::vector<JobState>* out = nullptr) {
+                int64_t lab_stride, bool accept = false, std::vector<JobState>* out = nullptr,
+                int prec = BM_FP32) {
   const int J = b.njobs, first = b.first, k = b.k, cp = b.cp;
   LloydSetup L;
-  BM_TRY(lloyd_setup(c, b, max_iter, tol, labels, lab_stride, accept, &L));
+  BM_TRY(lloyd_setup(c, b, max_iter, tol, labels, lab_stride, accept, &L, prec));
   TileMap tm = make_tiles(b.sizes, choose_tile_pts(b.sizes));
   BM_TRY(upload_tiles(c, tm));
   BM_TRY(upload(c, P<int64_t>(c->sizes) + first, b.sizes.data(), J * sizeof(int64_t)));
@@ -526,7 +533,7 @@ int lloyd_batch(bm_ctx* c, const BatchView& b, int max_iter, double tol, int32_t
 
 // Objective of each job of the batch (no centroid update): fjob[first + j].
 int objective_batch(bm_ctx* c, const BatchView& b, int32_t* labels, int64_t lab_stride,
-                    int64_t max_chunks, bool near) {
+                    int64_t max_chunks, bool near, int prec = BM_FP32) {
   const int J = b.njobs, first = b.first, k = b.k, cp = b.cp;
   TileMap tm = make_tiles(b.sizes, choose_tile_pts(b.sizes));
   BM_TRY(upload_tiles(c, tm));
@@ -556,7 +563,9 @@ int objective_batch(bm_ctx* c, const BatchView& b, int32_t* labels, int64_t lab_
   a.cnt = nullptr;
   a.scale = nullptr;
   a.st = nullptr;
-  if (cp > bm::kMaxRegDim)
+  if (cp > bm::kMaxRegDim && prec == BM_BF16)
+    HIP_TRY(c, bm::launch_assign_wide_bf16(c->stream, a, tm.total, false));
+  else if (cp > bm::kMaxRegDim)
     HIP_TRY(c, bm::launch_assign_wide(c->stream, a, tm.total, false));
   else
     HIP_TRY(c, bm::launch_assign(c->stream, a, tm.total, false));
@@ -862,7 +871,8 @@ int round_persistent(bm_ctx* c, const float* X, const bm_params& p, int t,
 }
 
 int check_prec(bm_ctx* c, int prec) {
-  if (prec != BM_FP32) return c->fail(BM_E_ARG, "precision %d is not available (BM_FP32 only)", prec);
+  if (prec != BM_FP32 && prec != BM_BF16)
+    return c->fail(BM_E_ARG, "precision %d is not one of BM_FP32, BM_BF16", prec);
   return BM_OK;
 }
 
@@ -967,7 +977,7 @@ int validate_params(bm_ctx* c, const bm_params* p) {
 // store for the whole call.
 // ---------------------------------------------------------------------------
 struct ServeWorker {
-  int d = 0, k = 0, w = 0, group = 0;
+  int d = 0, k = 0, w = 0;
   uint32_t rng_worker = 0;
   int64_t off_c = 0, off_deg = 0;  // offsets in the incumbent store
   double fhat = std::numeric_limits<double>::infinity();
@@ -980,6 +990,7 @@ struct ServeWorker {
 
 struct ServeGroup {
   int d = 0, k = 0, n = 0, cp = 0;
+  int prec = BM_FP32;  // BM_BF16 only for wide points (the narrow kernels have one precision)
   bm_ctx* c = nullptr;
   int slots = 0;
   int64_t s_max = 0;
@@ -1064,7 +1075,7 @@ int serve_admit(bm_ctx* c, ServeState& st, std::vector<ServeWorker>& workers,
                                  P<uint64_t>(gc->rkeys), P<int32_t>(gc->idx), gc->max_s,
                                  P<float>(gc->S), Sj, cp));
     all.sizes = sz;
-    BM_TRY(objective_batch(gc, all, nullptr, 0, gc->max_chunks, false));
+    BM_TRY(objective_batch(gc, all, nullptr, 0, gc->max_chunks, false, G.prec));
     std::vector<double> fr(J);
     BM_TRY(readback(gc, P<double>(gc->fjob), J * sizeof(double), fr.data()));
     for (int i : re) workers[job_worker[adm[i].first]].fhat = fr[adm[i].second];
@@ -1151,8 +1162,8 @@ int serve_impl(bm_ctx* c, const bm_dataset* ds, int nds, const bm_job* jobs, int
   ServeState st;
   std::vector<ServeWorker> workers;
   std::map<std::tuple<int, int, int>, int> wmap;
-  std::map<std::pair<int, int>, int> gmap;
-  std::vector<int> job_worker(njobs);
+  std::map<std::tuple<int, int, int>, int> gmap;
+  std::vector<int> job_worker(njobs), job_group(njobs);
   for (int j = 0; j < njobs; ++j) {
     const bm_job& jb = jobs[j];
     const auto key = std::make_tuple(jb.dataset, jb.k, jb.worker);
@@ -1164,23 +1175,27 @@ int serve_impl(bm_ctx* c, const bm_dataset* ds, int nds, const bm_job* jobs, int
       W.w = jb.worker;
       W.rng_worker = ((uint32_t)jb.dataset << 20) | ((uint32_t)jb.k << 10) | (uint32_t)jb.worker;
       W.ndeg = jb.k;
-      const auto gk = std::make_pair(jb.dataset, jb.k);
-      auto gi = gmap.find(gk);
-      if (gi == gmap.end()) {
-        ServeGroup G;
-        G.d = jb.dataset;
-        G.k = jb.k;
-        G.n = ds[jb.dataset].n;
-        G.cp = round_up4(G.n);
-        gi = gmap.emplace(gk, (int)st.groups.size()).first;
-        st.groups.push_back(std::move(G));
-      }
-      W.group = gi->second;
       it = wmap.emplace(key, (int)workers.size()).first;
       workers.push_back(std::move(W));
     }
     job_worker[j] = it->second;
-    ServeGroup& G = st.groups[workers[it->second].group];
+    // jobs of one (dataset, k) share launches; wide points also split by precision
+    const int n = ds[jb.dataset].n;
+    const int prec = round_up4(n) > bm::kMaxRegDim ? jb.prec : BM_FP32;
+    const auto gk = std::make_tuple(jb.dataset, jb.k, prec);
+    auto gi = gmap.find(gk);
+    if (gi == gmap.end()) {
+      ServeGroup G;
+      G.d = jb.dataset;
+      G.k = jb.k;
+      G.n = n;
+      G.cp = round_up4(n);
+      G.prec = prec;
+      gi = gmap.emplace(gk, (int)st.groups.size()).first;
+      st.groups.push_back(std::move(G));
+    }
+    job_group[j] = gi->second;
+    ServeGroup& G = st.groups[gi->second];
     G.s_max = std::max(G.s_max, jb.s);
     G.jobs += 1;
   }
@@ -1229,7 +1244,7 @@ int serve_impl(bm_ctx* c, const bm_dataset* ds, int nds, const bm_job* jobs, int
     b.S = P<float>(G.c->S);
     b.S_stride = G.c->max_s * G.cp;
     b.ld = G.cp;
-    rc = lloyd_setup(G.c, b, sp.max_iter, sp.tol, nullptr, 0, true, &G.L);
+    rc = lloyd_setup(G.c, b, sp.max_iter, sp.tol, nullptr, 0, true, &G.L, G.prec);
     if (rc != BM_OK) return c->fail(rc, "%s", G.c->err.c_str());
   }
   HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -1260,12 +1275,12 @@ int serve_impl(bm_ctx* c, const bm_dataset* ds, int nds, const bm_job* jobs, int
     std::vector<std::vector<std::pair<int, int>>> adm(st.groups.size());
     for (int j : heads) {
       ServeWorker& W = workers[job_worker[j]];
-      ServeGroup& G = st.groups[W.group];
+      ServeGroup& G = st.groups[job_group[j]];
       const int64_t bytes = serve_job_bytes(jobs[j].s, G.n, G.k);
       if (G.running >= G.slots || inflight + bytes > sp.budget_bytes) continue;
       int q = 0;
       while (G.slot_job[q] >= 0) ++q;
-      adm[W.group].push_back({j, q});
+      adm[job_group[j]].push_back({j, q});
       W.queue.pop_front();
       W.busy = true;
       G.slot_job[q] = j;
@@ -1508,7 +1523,7 @@ BM_API int bm_lloyd(bm_ctx* c, const float* S, int64_t s, int32_t n, int32_t k, 
   b.S_stride = 0;
   b.ld = n;
   b.sizes = {s};
-  BM_TRY(lloyd_batch(c, b, max_iter, tol, labels_out, 0));
+  BM_TRY(lloyd_batch(c, b, max_iter, tol, labels_out, 0, false, nullptr, prec));
   HIP_TRY(c, bm::launch_unpad(c->stream, P<float>(c->Cp), cp, n, k, 1, C, 0));
   if (degenerate_out)
     HIP_TRY(c, hipMemcpyAsync(degenerate_out, c->deg_work.p, (size_t)k, hipMemcpyDeviceToDevice, c->stream));
@@ -1543,7 +1558,8 @@ BM_API int bm_objective(bm_ctx* c, const float* X, int64_t m, int32_t n, const f
   b.S_stride = 0;
   b.ld = n;
   b.sizes = {m};
-  BM_TRY(objective_batch(c, b, labels_out, 0, (m + bm::kWG - 1) / bm::kWG, near_ties_out != nullptr));
+  BM_TRY(objective_batch(c, b, labels_out, 0, (m + bm::kWG - 1) / bm::kWG, near_ties_out != nullptr,
+                         prec));
   double f;
   BM_TRY(readback(c, c->fjob.p, sizeof(double), &f));
   *f_out = f;
@@ -1771,7 +1787,7 @@ BM_API int bm_bigmeans_run(bm_ctx* c, const float* X, const bm_params* params, f
       b.S_stride = Sj;
       b.ld = cp;
       b.sizes = szs;  // zero-size jobs produce no tiles and f = 0
-      BM_TRY(objective_batch(c, b, nullptr, 0, c->max_chunks, false));
+      BM_TRY(objective_batch(c, b, nullptr, 0, c->max_chunks, false, p.prec));
       std::vector<double> fr(W);
       BM_TRY(readback(c, c->fjob.p, W * sizeof(double), fr.data()));
       for (int w : rec) fhat[w] = fr[w];
@@ -1820,7 +1836,7 @@ BM_API int bm_bigmeans_run(bm_ctx* c, const float* X, const bm_params* params, f
         // replaces the incumbent on a strict improvement)
         HIP_TRY(c, hipEventRecord(c->ev1, st));
         std::vector<JobState> fin;
-        BM_TRY(lloyd_batch(c, b, p.max_iter, p.tol, nullptr, 0, true, &fin));
+        BM_TRY(lloyd_batch(c, b, p.max_iter, p.tol, nullptr, 0, true, &fin, p.prec));
         HIP_TRY(c, hipEventRecord(c->ev2, st));
         HIP_TRY(c, hipEventSynchronize(c->ev2));
         float ms = 0.f;
@@ -1875,7 +1891,7 @@ BM_API int bm_bigmeans_run(bm_ctx* c, const float* X, const bm_params* params, f
   fb.S_stride = 0;  // shared sample
   fb.ld = cp;
   fb.sizes.assign(W, s_opt);
-  BM_TRY(objective_batch(c, fb, nullptr, 0, c->max_chunks, false));
+  BM_TRY(objective_batch(c, fb, nullptr, 0, c->max_chunks, false, p.prec));
   std::vector<double> ffin(W);
   BM_TRY(readback(c, c->fjob.p, W * sizeof(double), ffin.data()));
   int best = -1;
@@ -1904,7 +1920,7 @@ BM_API int bm_bigmeans_run(bm_ctx* c, const float* X, const bm_params* params, f
   xb.S_stride = 0;
   xb.ld = n;
   xb.sizes = {m};
-  BM_TRY(objective_batch(c, xb, Y_out, 0, (m + bm::kWG - 1) / bm::kWG, false));
+  BM_TRY(objective_batch(c, xb, Y_out, 0, (m + bm::kWG - 1) / bm::kWG, false, p.prec));
   double f_full;
   BM_TRY(readback(c, c->fjob.p, sizeof(double), &f_full));
   HIP_TRY(c, hipEventRecord(c->ev1, st));

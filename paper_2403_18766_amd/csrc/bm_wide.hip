@@ -20,14 +20,29 @@
 //
 // Lloyd labels ping-pong between two arrays (assignment q writes array q mod
 // 2), so the update kernel sees the old and the new label of every point.
+//
+// BF16 variant (k_assign_wide<SUMS, true>): the dot products run on the BF16
+// matrix cores (v_mfma_f32_32x32x16_bf16, FP32 accumulation).  Every FP32
+// coordinate is split while it is staged into a BF16 high part h = bf16(v)
+// and a BF16 residual l = bf16(v - h), and x.c is taken as
+// xh.ch + xh.cl + xl.ch: the dropped terms are below 3.01 u_b^2 |x_d||c_d|
+// per coordinate (u_b = 2^-8), so the error bound stays near the FP32 one
+// and so does the share of points the FP32 direct form re-decides.  With a
+// single BF16 product the bound would be about 2^-7 ||x|| ||c||, and on
+// unit-norm data with 100 clusters in 768-D about two thirds of the points
+// would need the re-decision.  Re-decisions, the winner's distance and the
+// objective are the FP32 direct form of the FP32 rows, as in the FP32 path.
 
 #include <math.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 #include <hip/hip_runtime.h>
 
 #include "bm_device.h"
 #include "bm_internal.h"
+#include "bm_precision.h"
 
 namespace bm {
 namespace {
@@ -40,6 +55,24 @@ constexpr int kUpdDims = 64;       // dimensions per update workgroup
 constexpr int kUpdPts = 8192;      // points per update workgroup
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kRowB = 2 * kDK + 8;  // BF16 LDS row: 32 high parts, 32 residuals, 8 pad (144 B)
+constexpr float kUB2 = 1.52587890625e-5f;  // u_b^2 = 2^-16 (u_b = 2^-8, unit roundoff of BF16)
+
+// High parts and residuals of four FP32 values (round to nearest even; the
+// difference v - h is exact in FP32).
+__device__ inline void split_bf16(const float4 v, bf16x4& h, bf16x4& l) {
+  h[0] = (__bf16)v.x;
+  h[1] = (__bf16)v.y;
+  h[2] = (__bf16)v.z;
+  h[3] = (__bf16)v.w;
+  l[0] = (__bf16)(v.x - (float)h[0]);
+  l[1] = (__bf16)(v.y - (float)h[1]);
+  l[2] = (__bf16)(v.z - (float)h[2]);
+  l[3] = (__bf16)(v.w - (float)h[3]);
+}
 
 // Direct-form squared distance over the padded width: partial sum d mod 4,
 // then (p0 + p1) + (p2 + p3).  Padding is zero on both sides, so the value
@@ -91,7 +124,33 @@ struct WideShared {
   int red_i[4];
 };
 
-template <bool SUMS>
+struct __align__(16) WideSharedB {
+  __bf16 S[kChunk * kRowB];  // row r: high parts of its 32 dimensions, then their residuals
+  __bf16 C[kCG * kRowB];
+  double red_f[4];
+  int red_i[4];
+};
+
+// Row of the staging loops: 4 consecutive dimensions d .. d + 3 of row r of
+// the chunk (zero past the point count, past n and past cp).
+__device__ inline float4 stage_point(const float* __restrict__ S, int64_t row, int ld, int d, int n,
+                                     int cp, int vec, bool in) {
+  float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (in) {
+    const float* src = S + row * (int64_t)ld + d;
+    if (vec) {
+      if (d < cp) v = *reinterpret_cast<const float4*>(src);
+    } else {
+      v.x = d < n ? src[0] : 0.f;
+      v.y = d + 1 < n ? src[1] : 0.f;
+      v.z = d + 2 < n ? src[2] : 0.f;
+      v.w = d + 3 < n ? src[3] : 0.f;
+    }
+  }
+  return v;
+}
+
+template <bool SUMS, bool BF>
 __global__ __launch_bounds__(256, 2) void k_assign_wide(AssignArgs a) {
   const int job = a.tile_job[blockIdx.x];
   int parity = 0;
@@ -113,7 +172,7 @@ __global__ __launch_bounds__(256, 2) void k_assign_wide(AssignArgs a) {
   const bool want_near = a.tnear != nullptr;
   const int vec = a.vec;
 
-  __shared__ WideShared sh;
+  __shared__ typename std::conditional<BF, WideSharedB, WideShared>::type sh;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int half = lane >> 5, col = lane & 31;
 
@@ -122,10 +181,13 @@ __global__ __launch_bounds__(256, 2) void k_assign_wide(AssignArgs a) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) cmax2 = fmaxf(cmax2, __shfl_xor(cmax2, off, 64));
   const float cmax = sqrtf(cmax2) * 1.0000002f;
-  // any summation order of cp products: gamma_{cp+1}
-  const float terms = (float)(cp + 1);
+  // any summation order of the products: gamma_{cp+1} (FP32), gamma_{3cp+1}
+  // (three split products per dimension, whose magnitudes add up to at most
+  // 1.02 |x_d||c_d|) plus the dropped split terms (BF16)
+  const float terms = BF ? (float)(3 * cp + 1) : (float)(cp + 1);
   const float gam = terms * kU / (1.f - terms * kU);
-  const float kB = 2.f * (2.f * gam + 2.f * kU);
+  const float kB = BF ? 2.f * (2.f * (3.2f * kUB2 + 1.02f * gam) + 2.1f * kU)
+                      : 2.f * (2.f * gam + 2.f * kU);
 
   for (int64_t cb = t0; cb < t1; cb += kChunk) {
     const int np = (int)min((int64_t)kChunk, t1 - cb);  // valid points of the chunk
@@ -149,56 +211,99 @@ __global__ __launch_bounds__(256, 2) void k_assign_wide(AssignArgs a) {
           for (int v = 0; v < 16; ++v) acc[b][t][v] = 0.f;
       for (int d0 = 0; d0 < cp; d0 += kDK) {
         __syncthreads();  // the previous stage has been consumed
-        // stage the chunk's rows: 256 x 32 floats, 8 consecutive dims per load group
-        for (int e = tid; e < kChunk * (kDK / 4); e += 256) {
-          const int r = e / (kDK / 4), q = e - r * (kDK / 4);
-          const int d = d0 + 4 * q;
-          float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-          if (r < np) {
-            const float* src = S + (cb + r) * (int64_t)ld + d;
-            if (vec) {
-              if (d < cp) v = *reinterpret_cast<const float4*>(src);
-            } else {
-              v.x = d < n ? src[0] : 0.f;
-              v.y = d + 1 < n ? src[1] : 0.f;
-              v.z = d + 2 < n ? src[2] : 0.f;
-              v.w = d + 3 < n ? src[3] : 0.f;
+        if constexpr (!BF) {
+          // stage the chunk's rows: 256 x 32 floats, 8 consecutive dims per load group
+          for (int e = tid; e < kChunk * (kDK / 4); e += 256) {
+            const int r = e / (kDK / 4), q = e - r * (kDK / 4);
+            const float4 v = stage_point(S, cb + r, ld, d0 + 4 * q, n, cp, vec, r < np);
+            float* dst = sh.S + r * kRow + 4 * q;
+            dst[0] = v.x;
+            dst[1] = v.y;
+            dst[2] = v.z;
+            dst[3] = v.w;
+          }
+          // stage the group's centres: 128 x 32 floats (rows past k are zero)
+          for (int e = tid; e < kCG * (kDK / 4); e += 256) {
+            const int r = e / (kDK / 4), q = e - r * (kDK / 4);
+            const int d = d0 + 4 * q;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (r < ng && d < cp) v = *reinterpret_cast<const float4*>(C + (int64_t)(g0 + r) * cp + d);
+            float* dst = sh.C + r * kRow + 4 * q;
+            dst[0] = v.x;
+            dst[1] = v.y;
+            dst[2] = v.z;
+            dst[3] = v.w;
+          }
+          __syncthreads();
+          // lane (half, col): A = centre (tile*32 + col) at dim kk + half,
+          //                   B = point (wv*64 + b*32 + col) at dim kk + half
+          for (int kk = 0; kk < kDK; kk += 2) {
+            float bv[2];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+              bv[b] = sh.S[(wv * 64 + b * 32 + col) * kRow + kk + half];
+              if (g0 == 0) xxp[b] = fmaf(bv[b], bv[b], xxp[b]);
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+              const float av = sh.C[(t * 32 + col) * kRow + kk + half];
+#pragma unroll
+              for (int b = 0; b < 2; ++b)
+                acc[b][t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv[b], acc[b][t], 0, 0, 0);
             }
           }
-          float* dst = sh.S + r * kRow + 4 * q;
-          dst[0] = v.x;
-          dst[1] = v.y;
-          dst[2] = v.z;
-          dst[3] = v.w;
-        }
-        // stage the group's centres: 128 x 32 floats (rows past k are zero)
-        for (int e = tid; e < kCG * (kDK / 4); e += 256) {
-          const int r = e / (kDK / 4), q = e - r * (kDK / 4);
-          const int d = d0 + 4 * q;
-          float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-          if (r < ng && d < cp) v = *reinterpret_cast<const float4*>(C + (int64_t)(g0 + r) * cp + d);
-          float* dst = sh.C + r * kRow + 4 * q;
-          dst[0] = v.x;
-          dst[1] = v.y;
-          dst[2] = v.z;
-          dst[3] = v.w;
-        }
-        __syncthreads();
-        // lane (half, col): A = centre (tile*32 + col) at dim kk + half,
-        //                   B = point (wv*64 + b*32 + col) at dim kk + half
-        for (int kk = 0; kk < kDK; kk += 2) {
-          float bv[2];
-#pragma unroll
-          for (int b = 0; b < 2; ++b) {
-            bv[b] = sh.S[(wv * 64 + b * 32 + col) * kRow + kk + half];
-            if (g0 == 0) xxp[b] = fmaf(bv[b], bv[b], xxp[b]);
+        } else {
+          // stage the chunk's rows split into high parts and residuals
+          for (int e = tid; e < kChunk * (kDK / 4); e += 256) {
+            const int r = e / (kDK / 4), q = e - r * (kDK / 4);
+            const float4 v = stage_point(S, cb + r, ld, d0 + 4 * q, n, cp, vec, r < np);
+            bf16x4 h, l;
+            split_bf16(v, h, l);
+            __bf16* dst = sh.S + r * kRowB + 4 * q;
+            *reinterpret_cast<bf16x4*>(dst) = h;
+            *reinterpret_cast<bf16x4*>(dst + kDK) = l;
           }
+          for (int e = tid; e < kCG * (kDK / 4); e += 256) {
+            const int r = e / (kDK / 4), q = e - r * (kDK / 4);
+            const int d = d0 + 4 * q;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (r < ng && d < cp) v = *reinterpret_cast<const float4*>(C + (int64_t)(g0 + r) * cp + d);
+            bf16x4 h, l;
+            split_bf16(v, h, l);
+            __bf16* dst = sh.C + r * kRowB + 4 * q;
+            *reinterpret_cast<bf16x4*>(dst) = h;
+            *reinterpret_cast<bf16x4*>(dst + kDK) = l;
+          }
+          __syncthreads();
+          // lane (half, col): A = centre (tile*32 + col), B = point
+          // (wv*64 + b*32 + col), both at dims ks + 8 half .. ks + 8 half + 7
+          for (int ks = 0; ks < kDK; ks += 16) {
+            bf16x8 xh[2], xl[2];
 #pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const float av = sh.C[(t * 32 + col) * kRow + kk + half];
+            for (int b = 0; b < 2; ++b) {
+              const __bf16* p = sh.S + (wv * 64 + b * 32 + col) * kRowB + ks + 8 * half;
+              xh[b] = *reinterpret_cast<const bf16x8*>(p);
+              xl[b] = *reinterpret_cast<const bf16x8*>(p + kDK);
+              if (g0 == 0) {
 #pragma unroll
-            for (int b = 0; b < 2; ++b)
-              acc[b][t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv[b], acc[b][t], 0, 0, 0);
+                for (int q = 0; q < 8; ++q) {
+                  const float v = (float)xh[b][q] + (float)xl[b][q];  // exact
+                  xxp[b] = fmaf(v, v, xxp[b]);
+                }
+              }
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+              const __bf16* p = sh.C + (t * 32 + col) * kRowB + ks + 8 * half;
+              const bf16x8 ch = *reinterpret_cast<const bf16x8*>(p);
+              const bf16x8 cl = *reinterpret_cast<const bf16x8*>(p + kDK);
+#pragma unroll
+              for (int b = 0; b < 2; ++b) {
+                acc[b][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cl, xh[b], acc[b][t], 0, 0, 0);
+                acc[b][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ch, xl[b], acc[b][t], 0, 0, 0);
+                acc[b][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ch, xh[b], acc[b][t], 0, 0, 0);
+              }
+            }
           }
         }
       }
@@ -450,9 +555,18 @@ __global__ __launch_bounds__(256) void k_finalize_wide(FinalizeArgs a) {
 hipError_t launch_assign_wide(hipStream_t st, const AssignArgs& a, int32_t ntiles, bool sums) {
   if (a.tile_pts % kChunk != 0) return hipErrorInvalidValue;
   if (sums)
-    hipLaunchKernelGGL(k_assign_wide<true>, dim3(ntiles), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_assign_wide<true, false>), dim3(ntiles), dim3(256), 0, st, a);
   else
-    hipLaunchKernelGGL(k_assign_wide<false>, dim3(ntiles), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_assign_wide<false, false>), dim3(ntiles), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_assign_wide_bf16(hipStream_t st, const AssignArgs& a, int32_t ntiles, bool sums) {
+  if (a.tile_pts % kChunk != 0) return hipErrorInvalidValue;
+  if (sums)
+    hipLaunchKernelGGL((k_assign_wide<true, true>), dim3(ntiles), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_assign_wide<false, true>), dim3(ntiles), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
