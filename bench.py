@@ -31,6 +31,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Lloyd point·centre dists/s & time to f(C,X) within 1% of oracle; p99 latency"
 PEAK_FP32_VECTOR_TFLOPS = 157.3
+PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0}  # dense matrix-core peaks of the MI355X
+PEAK_HBM_GBS = 8000.0
 
 WORKLOAD = dict(name="aniso28", k=25, workers=32, rounds_T=5, passes_p=10, s_min=4096,
                 s_max=65536)
@@ -114,7 +116,7 @@ def serve_run(torch, dev, njobs):
         s = min(SERVE["s_max"], int(math.floor(math.exp(r.uniform(ls, lb)))))
         jobs.append(dict(arrival=t, s=s, dataset=int(r.integers(len(Xs))),
                          k=int(SERVE["ks"][r.integers(len(SERVE["ks"]))]),
-                         worker=int(r.integers(SERVE["workers"]))))
+                         worker=int(r.integers(SERVE["workers"])), prec=int(r.integers(2))))
     log("serving", njobs, "jobs")
     res, st = api.serve(Xs, jobs, seed=0, budget_bytes=SERVE["budget_gb"] << 30, max_slots=64,
                         paced=True)
@@ -124,12 +126,69 @@ def serve_run(torch, dev, njobs):
     return {"workload": (f"3 resident data sets of {SERVE['m']:,} points (noisy Gaussian mixtures, "
                          f"n = 16, 64, 256); {njobs} jobs, Poisson arrivals at "
                          f"{SERVE['rate']:.0f}/s; k in (10, 50, 200); s log-uniform in "
-                         f"[{SERVE['s_min']}, {SERVE['s_max']}]; 32 workers per (data set, k); "
+                         f"[{SERVE['s_min']}, {SERVE['s_max']}]; FP32 or BF16 with equal odds (matrix-core "
+                         f"distances at n = 256); 32 workers per (data set, k); "
                          f"{SERVE['budget_gb']} GiB budget"),
             "jobs_per_s": njobs / st["seconds"], "p50_latency_ms": float(np.percentile(lat, 50)),
             "p99_latency_ms": float(np.percentile(lat, 99)), "wall_s": st["seconds"],
             "lloyd_steps": st["steps"], "peak_running": st["peak_running"],
             "peak_bytes": st["peak_bytes"]}
+
+
+PREC = dict(m=2_000_000, n=768, k=100, workers=16, s=131_072, rounds_T=2, passes_p=10)
+
+
+def precision_run(torch, dev):
+    """Algorithm 1 on 2,000,000 unit vectors in 768-D (100 vMF clusters),
+    k = 100, 16 workers with fixed samples of 131,072: once with FP32 and once
+    with BF16 matrix-core distances.  Per precision: wall time, Lloyd
+    distances/s, and the assignment + update kernels timed with HIP events
+    (algorithmic FLOP/s against the precision's matrix-core peak, and
+    algorithmic bytes/s: each sample row read once per Lloyd step)."""
+    from paper_2403_18766_amd import _lib, api, datagen
+    log("generating the vmf768 workload on the device")
+    X = datagen.vmf_mixture_device(PREC["m"] // 100, PREC["n"], 100, dev, seed=0)
+    torch.cuda.synchronize()
+    n, k, s = PREC["n"], PREC["k"], PREC["s"]
+    api.reserve(dev, s, n, k, PREC["workers"])
+    out = {"workload": (f"{PREC['m']:,} unit vectors in {n}-D from 100 von Mises-Fisher clusters "
+                        f"(kappa U[50,200]), k={k}, {PREC['workers']} workers, fixed s={s:,}, "
+                        f"T={PREC['rounds_T']} rounds x p={PREC['passes_p']} passes, "
+                        "one launch per Lloyd step")}
+    for name, prec in (("f32", _lib.BM_FP32), ("bf16", _lib.BM_BF16)):
+        common = dict(k=k, workers=PREC["workers"], s_min=s, s_max=s,
+                      size_policy=_lib.BM_SIZE_FIXED, seed=0, batched=2, prec=prec)
+        api.bigmeans_run(X, api.RunParams(rounds_T=1, passes_p=1, **common), labels=False)
+        torch.cuda.synchronize()
+        api.set_profiling(dev, True)
+        t0 = time.perf_counter()
+        r = api.bigmeans_run(X, api.RunParams(rounds_T=PREC["rounds_T"], passes_p=PREC["passes_p"],
+                                              **common), labels=False)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = api.get_stats(dev)
+        api.set_profiling(dev, False)
+        ksec = st["assign_seconds"]
+        tflops = st["assign_dists"] * 2.0 * n / ksec / 1e12 if ksec > 0 else 0.0
+        gbs = st["assign_dists"] * 4.0 * n / k / ksec / 1e9 if ksec > 0 else 0.0
+        out[name] = {"seconds": wall, "lloyd_dists": r["lloyd_dists"],
+                     "dists_per_s": r["lloyd_dists"] / wall,
+                     "lloyd_phase_dists_per_s": r["lloyd_dists"] / r["lloyd_seconds"],
+                     "f_full": r["f_full"],
+                     "kernels": f"k_assign_wide<true,{'true' if name == 'bf16' else 'false'}> "
+                                "+ k_update_wide",
+                     "kernel_launches": st["assign_launches"],
+                     "kernel_avg_us": 1e6 * ksec / max(1, st["assign_launches"]),
+                     "kernel_dists_per_s": st["assign_dists"] / ksec if ksec > 0 else None,
+                     "achieved_tflops": tflops, "peak_tflops": PEAK_TFLOPS[name],
+                     "mfma_frac": tflops / PEAK_TFLOPS[name],
+                     "algorithmic_gbs": gbs, "hbm_frac": gbs / PEAK_HBM_GBS}
+        log("precision", name, "wall", wall, "f_full", r["f_full"])
+    out["bf16_speedup"] = out["f32"]["seconds"] / out["bf16"]["seconds"]
+    out["bf16_f_gap"] = (out["bf16"]["f_full"] - out["f32"]["f_full"]) / out["f32"]["f_full"]
+    del X
+    torch.cuda.empty_cache()
+    return out
 
 
 def reference_f(X):
@@ -156,6 +215,8 @@ def main():
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-target run")
     ap.add_argument("--serve-jobs", type=int, default=2000,
                     help="jobs of the serving measurement (0 skips it)")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the FP32 / BF16 matrix-core measurement")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed steps, copy 512 MiB three times (counter scaling)")
     ap.add_argument("--mode", type=int, default=1,
@@ -237,6 +298,7 @@ def main():
     cpu = None if args.no_cpu else cpu_baseline(X, args.cpu_workers, args.cpu_passes)
     del Xd
     serving = serve_run(torch, dev, args.serve_jobs) if args.serve_jobs > 0 else None
+    precision = None if args.no_precision else precision_run(torch, dev)
     f_full = results[-1]["f_full"]
     out = {
         "metric": METRIC, "value": value, "unit": "dists/s", "n_gpus": 1, "steps": args.steps,
@@ -258,6 +320,7 @@ def main():
         "time_to_target": ttt,
         "p99_latency_ms": serving["p99_latency_ms"] if serving else None,
         "serving": serving,
+        "precision": precision,
     }
     print(json.dumps(out), flush=True)
 

@@ -620,7 +620,10 @@ int kpp_batch(bm_ctx* c, const BatchView& b, const KppBatch& kb) {
   HIP_TRY(c, bm::launch_kpp_init(c->stream, a, J, smax));
   for (int step = 0; step < kb.steps; ++step) {
     HIP_TRY(c, bm::launch_kpp_step(c->stream, a, J));
-    HIP_TRY(c, bm::launch_kpp_pot(c->stream, a, J, smax));
+    if (cp > bm::kMaxRegDim)
+      HIP_TRY(c, bm::launch_kpp_pot_wide(c->stream, a, J, smax));
+    else
+      HIP_TRY(c, bm::launch_kpp_pot(c->stream, a, J, smax));
   }
   HIP_TRY(c, bm::launch_kpp_step(c->stream, a, J));  // commits the last step
   return BM_OK;
@@ -1144,7 +1147,10 @@ int serve_admit(bm_ctx* c, ServeState& st, std::vector<ServeWorker>& workers,
     HIP_TRY(c, bm::launch_kpp_init(str, a, A, smax));
     for (int step = 0; step < steps; ++step) {
       HIP_TRY(c, bm::launch_kpp_step(str, a, A));
-      HIP_TRY(c, bm::launch_kpp_pot(str, a, A, smax));
+      if (a.cp > bm::kMaxRegDim)
+        HIP_TRY(c, bm::launch_kpp_pot_wide(str, a, A, smax));
+      else
+        HIP_TRY(c, bm::launch_kpp_pot(str, a, A, smax));
     }
     HIP_TRY(c, bm::launch_kpp_step(str, a, A));  // commits the last step
   }

@@ -15,8 +15,11 @@
 // 2 x.c_j, a rigorous bound on its FP32 rounding error (any summation order
 // of cp terms), a direct-form re-decision of every point whose best two e are
 // closer than that bound (the whole wave evaluates one such point's centres
-// together), lowest index on ties, and the winner's distance in the direct
-// form sum_d (x_d - c_d)^2 (four partial sums by d mod 4).
+// together; four partial sums by d mod 4), lowest index on ties, and the
+// winner's distance in the direct form sum_d (x_d - c_d)^2, which each thread
+// accumulates from the LDS stages while the rows pass for the matrix cores
+// (for the previous label of its point), or in a second pass when some point
+// of the chunk changed its label.
 //
 // Lloyd labels ping-pong between two arrays (assignment q writes array q mod
 // 2), so the update kernel sees the old and the new label of every point.
@@ -48,7 +51,6 @@ namespace bm {
 namespace {
 
 constexpr int kDK = 32;            // dimensions per LDS stage
-constexpr int kRow = kDK + 1;      // LDS row stride in floats (column reads hit distinct banks)
 constexpr int kCG = 128;           // centres per group (four 32-wide MFMA tiles)
 constexpr int kChunk = 256;        // points per chunk (one per thread in the per-point phase)
 constexpr int kUpdDims = 64;       // dimensions per update workgroup
@@ -58,7 +60,6 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kRowB = 2 * kDK + 8;  // BF16 LDS row: 32 high parts, 32 residuals, 8 pad (144 B)
 constexpr float kUB2 = 1.52587890625e-5f;  // u_b^2 = 2^-16 (u_b = 2^-8, unit roundoff of BF16)
 
 // High parts and residuals of four FP32 values (round to nearest even; the
@@ -105,6 +106,42 @@ __device__ inline float dist_wide(const float* __restrict__ x, const float* __re
   return (p0 + p1) + (p2 + p3);
 }
 
+// Squared distance by a whole wave (x and c uniform): lane l takes the
+// 4-float groups l, l + 64, ... (the dimensions l, l + 64, ... when rows are
+// not 16-byte aligned), then a butterfly adds the 64 partial sums, so every
+// lane ends with the same value; the reads are coalesced.
+__device__ inline float dist_wave(const float* __restrict__ x, const float* __restrict__ c, int n,
+                                  int cp, int ld_is_vec) {
+  const int lane = threadIdx.x & 63;
+  float p = 0.f;
+  if (ld_is_vec) {
+    const float4* x4 = reinterpret_cast<const float4*>(x);
+    const float4* c4 = reinterpret_cast<const float4*>(c);
+    for (int q = lane; q < cp / 4; q += 64) {
+      const float4 a = x4[q], b = c4[q];
+      const float t0 = a.x - b.x, t1 = a.y - b.y, t2 = a.z - b.z, t3 = a.w - b.w;
+      p = fmaf(t0, t0, p);
+      p = fmaf(t1, t1, p);
+      p = fmaf(t2, t2, p);
+      p = fmaf(t3, t3, p);
+    }
+  } else {
+    for (int d = lane; d < n; d += 64) {
+      const float t = x[d] - c[d];
+      p = fmaf(t, t, p);
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) p += __shfl_xor(p, off, 64);
+  return p;
+}
+
+// min that propagates NaN from either operand.
+__device__ inline float kpp_min_nan(float a, float b) {
+  const float r = b < a ? b : a;
+  return (a != a || b != b) ? __builtin_nanf("") : r;
+}
+
 // Best and second-best (value, index) merge; on equal values the lower index
 // wins, so the result is the first minimum in index order.
 __device__ inline void top2_merge(float& e1, int& j1, float& e2, float oe1, int oj1, float oe2) {
@@ -117,18 +154,18 @@ __device__ inline void top2_merge(float& e1, int& j1, float& e2, float oe1, int 
   }
 }
 
-struct WideShared {
-  float S[kChunk * kRow];
-  float C[kCG * kRow];
+// LDS of one assignment workgroup: the chunk's rows and the centre group,
+// 32 dimensions of each (FP32).  Row strides: 33 floats for the FP32 matrix
+// cores (one float per lane and column reads hit distinct banks), 36 for the
+// BF16 ones (8 floats per lane read as two 16-byte words).
+template <bool BF>
+struct __align__(16) WideShared {
+  static constexpr int kR = BF ? 36 : 33;
+  float S[kChunk * kR];
+  float C[kCG * kR];
   double red_f[4];
   int red_i[4];
-};
-
-struct __align__(16) WideSharedB {
-  __bf16 S[kChunk * kRowB];  // row r: high parts of its 32 dimensions, then their residuals
-  __bf16 C[kCG * kRowB];
-  double red_f[4];
-  int red_i[4];
+  int flag;
 };
 
 // Row of the staging loops: 4 consecutive dimensions d .. d + 3 of row r of
@@ -150,14 +187,133 @@ __device__ inline float4 stage_point(const float* __restrict__ S, int64_t row, i
   return v;
 }
 
+// 4 consecutive dimensions d .. d + 3 of a row for a staging loop: all loads
+// of a stage are issued before the first LDS store.  Out-of-range slots read
+// row 0 / dimension 0 of the same array (always valid) and are zeroed.
+__device__ inline float4 stage_load(const float* __restrict__ S, int64_t row, int ld, int d, int n,
+                                    int cp, int vec, bool in) {
+  if (vec) {
+    const bool ok = in && d < cp;
+    const float4 v = *reinterpret_cast<const float4*>(S + (ok ? row * (int64_t)ld + d : 0));
+    return ok ? v : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  return stage_point(S, row, ld, d, n, cp, vec, in);
+}
+
+// One 32-dimension stage of the chunk's rows (256 x 32) and of the centre
+// group g0 (ng rows, zero past k) into LDS, in batches of kBatch float4 per
+// thread whose loads are all issued before their stores.
+constexpr int kBatch = 4;
+
+template <bool BF>
+__device__ inline void stage_store(float* dst, const float4 v) {
+  if constexpr (BF) {
+    *reinterpret_cast<float4*>(dst) = v;
+  } else {
+    dst[0] = v.x;
+    dst[1] = v.y;
+    dst[2] = v.z;
+    dst[3] = v.w;
+  }
+}
+
+template <bool BF>
+__device__ inline void stage_rows(WideShared<BF>& sh, const float* __restrict__ S, int64_t cb,
+                                  int np, const float* __restrict__ C, int g0, int ng, int d0,
+                                  int ld, int n, int cp, int vec, bool centres) {
+  constexpr int R = WideShared<BF>::kR;
+  constexpr int kPt = kChunk * (kDK / 4) / 256;  // float4 per thread: rows
+  constexpr int kCt = kCG * (kDK / 4) / 256;     // float4 per thread: centres
+  static_assert(kPt % kBatch == 0 && kCt % kBatch == 0, "staging batches");
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int u0 = 0; u0 < kPt; u0 += kBatch) {
+    float4 v[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int e = tid + (u0 + u) * 256, r = e / (kDK / 4), q = e - r * (kDK / 4);
+      v[u] = stage_load(S, cb + r, ld, d0 + 4 * q, n, cp, vec, r < np);
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int e = tid + (u0 + u) * 256, r = e / (kDK / 4), q = e - r * (kDK / 4);
+      stage_store<BF>(sh.S + r * R + 4 * q, v[u]);
+    }
+  }
+  if (!centres) return;
+#pragma unroll
+  for (int u0 = 0; u0 < kCt; u0 += kBatch) {
+    float4 w[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int e = tid + (u0 + u) * 256, r = e / (kDK / 4), q = e - r * (kDK / 4);
+      w[u] = stage_load(C, g0 + r, cp, d0 + 4 * q, cp, cp, 1, r < ng);
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int e = tid + (u0 + u) * 256, r = e / (kDK / 4), q = e - r * (kDK / 4);
+      stage_store<BF>(sh.C + r * R + 4 * q, w[u]);
+    }
+  }
+}
+
+// Direct-form partial sums of this thread's row (row tid of the stage) against
+// centre row cr of the stage, dimensions in increasing order into p[d mod 4]:
+// over all stages this is the order of dist_wide.
+template <bool BF>
+__device__ inline void stage_direct(const WideShared<BF>& sh, int cr, float (&p)[4]) {
+  constexpr int R = WideShared<BF>::kR;
+  const float* x = sh.S + threadIdx.x * R;
+  const float* c = sh.C + cr * R;
+#pragma unroll
+  for (int d = 0; d < kDK; d += 4) {
+    float xv[4], cv[4];
+    if constexpr (BF) {
+      const float4 a = *reinterpret_cast<const float4*>(x + d);
+      const float4 b = *reinterpret_cast<const float4*>(c + d);
+      xv[0] = a.x; xv[1] = a.y; xv[2] = a.z; xv[3] = a.w;
+      cv[0] = b.x; cv[1] = b.y; cv[2] = b.z; cv[3] = b.w;
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        xv[q] = x[d + q];
+        cv[q] = c[d + q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float t = xv[q] - cv[q];
+      p[q] = fmaf(t, t, p[q]);
+    }
+  }
+}
+
+// Eight consecutive FP32 values as BF16 high parts and residuals.
+__device__ inline void split8(const float* v, bf16x8& h, bf16x8& l) {
+  const float4 a = *reinterpret_cast<const float4*>(v);
+  const float4 b = *reinterpret_cast<const float4*>(v + 4);
+  bf16x4 h0, l0, h1, l1;
+  split_bf16(a, h0, l0);
+  split_bf16(b, h1, l1);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    h[q] = h0[q];
+    h[4 + q] = h1[q];
+    l[q] = l0[q];
+    l[4 + q] = l1[q];
+  }
+}
+
 template <bool SUMS, bool BF>
 __global__ __launch_bounds__(256, 2) void k_assign_wide(AssignArgs a) {
+  constexpr int R = WideShared<BF>::kR;
   const int job = a.tile_job[blockIdx.x];
-  int parity = 0;
+  int parity = 0, iter = 0;
   if (a.st) {
     const JobState st = a.st[job];
     if (!st.active) return;
     parity = st.iter & 1;
+    iter = st.iter;
   }
   const int64_t s = a.s[job];
   const int64_t t0 = (int64_t)a.tile_idx[blockIdx.x] * a.tile_pts;
@@ -168,11 +324,16 @@ __global__ __launch_bounds__(256, 2) void k_assign_wide(AssignArgs a) {
   const float* __restrict__ cn = a.cn + job * a.cn_stride;
   int32_t* const lbase = (parity && a.labels2) ? a.labels2 : a.labels;
   int32_t* __restrict__ lab = lbase ? lbase + job * a.lab_stride : nullptr;
+  // Lloyd step q >= 1 of a wide job: step q - 1 wrote the other label array;
+  // each point's previous label predicts its winner, whose distance is then
+  // accumulated while the rows pass through LDS
+  const int32_t* prev = nullptr;
+  if (a.st && a.labels2 && iter >= 1) prev = (parity ? a.labels : a.labels2) + job * a.lab_stride;
   double* tfj = a.tf + (int64_t)job * a.max_chunks;
   const bool want_near = a.tnear != nullptr;
   const int vec = a.vec;
 
-  __shared__ typename std::conditional<BF, WideSharedB, WideShared>::type sh;
+  __shared__ WideShared<BF> sh;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int half = lane >> 5, col = lane & 31;
 
@@ -191,6 +352,14 @@ __global__ __launch_bounds__(256, 2) void k_assign_wide(AssignArgs a) {
 
   for (int64_t cb = t0; cb < t1; cb += kChunk) {
     const int np = (int)min((int64_t)kChunk, t1 - cb);  // valid points of the chunk
+    const int64_t i = cb + tid;
+    const bool valid = tid < np;
+    int pl = -1;  // predicted winner
+    if (prev && valid) {
+      pl = prev[i];
+      if (pl < 0 || pl >= k) pl = -1;
+    }
+    float pw[4] = {0.f, 0.f, 0.f, 0.f};  // direct-form partial sums to pl
     float e1[2], e2[2];
     int j1[2];
     float xxp[2] = {0.f, 0.f};
@@ -200,9 +369,10 @@ __global__ __launch_bounds__(256, 2) void k_assign_wide(AssignArgs a) {
       e2[b] = __builtin_inff();
       j1[b] = 0;
     }
+    f32x16 acc[2][4];  // after the loop: the products of the last centre group
     for (int g0 = 0; g0 < k; g0 += kCG) {
       const int ng = min(kCG, k - g0);
-      f32x16 acc[2][4];
+      const bool mine = pl >= g0 && pl < g0 + ng;
 #pragma unroll
       for (int b = 0; b < 2; ++b)
 #pragma unroll
@@ -211,92 +381,46 @@ __global__ __launch_bounds__(256, 2) void k_assign_wide(AssignArgs a) {
           for (int v = 0; v < 16; ++v) acc[b][t][v] = 0.f;
       for (int d0 = 0; d0 < cp; d0 += kDK) {
         __syncthreads();  // the previous stage has been consumed
+        stage_rows<BF>(sh, S, cb, np, C, g0, ng, d0, ld, n, cp, vec, true);
+        __syncthreads();
+        if (mine) stage_direct<BF>(sh, pl - g0, pw);
         if constexpr (!BF) {
-          // stage the chunk's rows: 256 x 32 floats, 8 consecutive dims per load group
-          for (int e = tid; e < kChunk * (kDK / 4); e += 256) {
-            const int r = e / (kDK / 4), q = e - r * (kDK / 4);
-            const float4 v = stage_point(S, cb + r, ld, d0 + 4 * q, n, cp, vec, r < np);
-            float* dst = sh.S + r * kRow + 4 * q;
-            dst[0] = v.x;
-            dst[1] = v.y;
-            dst[2] = v.z;
-            dst[3] = v.w;
-          }
-          // stage the group's centres: 128 x 32 floats (rows past k are zero)
-          for (int e = tid; e < kCG * (kDK / 4); e += 256) {
-            const int r = e / (kDK / 4), q = e - r * (kDK / 4);
-            const int d = d0 + 4 * q;
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (r < ng && d < cp) v = *reinterpret_cast<const float4*>(C + (int64_t)(g0 + r) * cp + d);
-            float* dst = sh.C + r * kRow + 4 * q;
-            dst[0] = v.x;
-            dst[1] = v.y;
-            dst[2] = v.z;
-            dst[3] = v.w;
-          }
-          __syncthreads();
           // lane (half, col): A = centre (tile*32 + col) at dim kk + half,
           //                   B = point (wv*64 + b*32 + col) at dim kk + half
           for (int kk = 0; kk < kDK; kk += 2) {
             float bv[2];
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
-              bv[b] = sh.S[(wv * 64 + b * 32 + col) * kRow + kk + half];
+              bv[b] = sh.S[(wv * 64 + b * 32 + col) * R + kk + half];
               if (g0 == 0) xxp[b] = fmaf(bv[b], bv[b], xxp[b]);
             }
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-              const float av = sh.C[(t * 32 + col) * kRow + kk + half];
+              const float av = sh.C[(t * 32 + col) * R + kk + half];
 #pragma unroll
               for (int b = 0; b < 2; ++b)
                 acc[b][t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv[b], acc[b][t], 0, 0, 0);
             }
           }
         } else {
-          // stage the chunk's rows split into high parts and residuals
-          for (int e = tid; e < kChunk * (kDK / 4); e += 256) {
-            const int r = e / (kDK / 4), q = e - r * (kDK / 4);
-            const float4 v = stage_point(S, cb + r, ld, d0 + 4 * q, n, cp, vec, r < np);
-            bf16x4 h, l;
-            split_bf16(v, h, l);
-            __bf16* dst = sh.S + r * kRowB + 4 * q;
-            *reinterpret_cast<bf16x4*>(dst) = h;
-            *reinterpret_cast<bf16x4*>(dst + kDK) = l;
-          }
-          for (int e = tid; e < kCG * (kDK / 4); e += 256) {
-            const int r = e / (kDK / 4), q = e - r * (kDK / 4);
-            const int d = d0 + 4 * q;
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (r < ng && d < cp) v = *reinterpret_cast<const float4*>(C + (int64_t)(g0 + r) * cp + d);
-            bf16x4 h, l;
-            split_bf16(v, h, l);
-            __bf16* dst = sh.C + r * kRowB + 4 * q;
-            *reinterpret_cast<bf16x4*>(dst) = h;
-            *reinterpret_cast<bf16x4*>(dst + kDK) = l;
-          }
-          __syncthreads();
           // lane (half, col): A = centre (tile*32 + col), B = point
-          // (wv*64 + b*32 + col), both at dims ks + 8 half .. ks + 8 half + 7
+          // (wv*64 + b*32 + col), both at dims ks + 8 half .. ks + 8 half + 7,
+          // split into high parts and residuals as they are read
           for (int ks = 0; ks < kDK; ks += 16) {
             bf16x8 xh[2], xl[2];
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
-              const __bf16* p = sh.S + (wv * 64 + b * 32 + col) * kRowB + ks + 8 * half;
-              xh[b] = *reinterpret_cast<const bf16x8*>(p);
-              xl[b] = *reinterpret_cast<const bf16x8*>(p + kDK);
+              const float* p = sh.S + (wv * 64 + b * 32 + col) * R + ks + 8 * half;
+              split8(p, xh[b], xl[b]);
               if (g0 == 0) {
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                  const float v = (float)xh[b][q] + (float)xl[b][q];  // exact
-                  xxp[b] = fmaf(v, v, xxp[b]);
-                }
+                for (int q = 0; q < 8; ++q) xxp[b] = fmaf(p[q], p[q], xxp[b]);
               }
             }
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-              const __bf16* p = sh.C + (t * 32 + col) * kRowB + ks + 8 * half;
-              const bf16x8 ch = *reinterpret_cast<const bf16x8*>(p);
-              const bf16x8 cl = *reinterpret_cast<const bf16x8*>(p + kDK);
+              bf16x8 ch, cl;
+              split8(sh.C + (t * 32 + col) * R + ks + 8 * half, ch, cl);
 #pragma unroll
               for (int b = 0; b < 2; ++b) {
                 acc[b][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cl, xh[b], acc[b][t], 0, 0, 0);
@@ -340,14 +464,70 @@ __global__ __launch_bounds__(256, 2) void k_assign_wide(AssignArgs a) {
     const float pe1 = half ? e1[1] : e1[0];
     const float pe2 = half ? e2[1] : e2[0];
     const int pj1 = half ? j1[1] : j1[0];
-    const int64_t i = cb + tid;
-    const bool valid = tid < np;
     double fpart = 0.0;
     int near = 0;
-    const float* x = S + i * (int64_t)ld;
     const float B = kB * (sqrtf(xx) * cmax + cmax2);
     const bool recheck = valid && !((pe2 - pe1) > 2.f * B + 2.5e-5f * fabsf(pe2 + xx));
     int jw = pj1;
+    if (k <= kCG) {
+      // Re-decision among the candidates only: a centre j whose e_j exceeds
+      // the point's best e by more than 2 B + 2.5e-5 |e_j + ||x||^2| is
+      // certified farther than the winner and not within the near-tie band.
+      // Lane (half, col) marks, for point col of each block, the candidates
+      // among its centres (bit 16 t + v for centre 32 t + 8 (v / 4) + 4 half
+      // + v % 4); then the wave takes the flagged points one at a time and
+      // their candidates one at a time (lanes over the dimensions).
+      unsigned long long cmask[2];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int owner = b * 32 + col;
+        const float E1 = __shfl(pe1, owner, 64);
+        const float Bb = __shfl(B, owner, 64);
+        const float XX = __shfl(xx, owner, 64);
+        unsigned long long m = 0ull;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const int c = t * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
+            if (c < k) {
+              const float e = fmaf(-2.f, acc[b][t][v], cn[c]);
+              if (!((e - E1) > 2.f * Bb + 2.5e-5f * fabsf(e + XX))) m |= 1ull << (t * 16 + v);
+            }
+          }
+        }
+        cmask[b] = m;
+      }
+      unsigned long long pending = __ballot(recheck);
+      while (pending) {
+        const int src = __ffsll(pending) - 1;
+        pending &= pending - 1;
+        const int sb = src >> 5, sc = src & 31;
+        const unsigned long long mb = sb ? cmask[1] : cmask[0];
+        unsigned long long mh[2];
+        mh[0] = ((unsigned long long)__builtin_amdgcn_readlane((int)(mb >> 32), sc) << 32) |
+                (unsigned int)__builtin_amdgcn_readlane((int)(mb & 0xffffffffull), sc);
+        mh[1] = ((unsigned long long)__builtin_amdgcn_readlane((int)(mb >> 32), sc + 32) << 32) |
+                (unsigned int)__builtin_amdgcn_readlane((int)(mb & 0xffffffffull), sc + 32);
+        const float* xs = S + (cb + wv * 64 + src) * (int64_t)ld;
+        float b1 = __builtin_inff(), b2 = __builtin_inff();
+        int jb = 0;
+        for (int h = 0; h < 2; ++h) {
+          unsigned long long mm = mh[h];
+          while (mm) {
+            const int bit = __ffsll(mm) - 1;
+            mm &= mm - 1;
+            const int c = (bit >> 4) * 32 + 8 * ((bit & 15) >> 2) + 4 * h + (bit & 3);
+            const float dd = dist_wave(xs, C + (int64_t)c * cp, n, cp, vec);
+            top2_merge(b1, jb, b2, dd, c, __builtin_inff());
+          }
+        }
+        if (lane == src) {
+          jw = jb;
+          if (b2 - b1 < 1e-5f * b2) near = 1;
+        }
+      }
+    } else {
     // direct-form re-decision, one flagged point at a time by the whole wave:
     // lane l takes the centres l, l + 64, ... in order, then the best and
     // second best merge across lanes (lowest index on equal distances)
@@ -380,8 +560,32 @@ __global__ __launch_bounds__(256, 2) void k_assign_wide(AssignArgs a) {
         if (b2 - b1 < 1e-5f * b2) near = 1;
       }
     }
+    }
+    // winner's distance: the accumulated one when the prediction holds, else a
+    // second pass of the rows through LDS for the whole chunk (same order)
+    const bool miss = valid && jw != pl;
+    if (tid == 0) sh.flag = 0;
+    __syncthreads();
+    if (miss) sh.flag = 1;
+    __syncthreads();
+    if (sh.flag) {
+      if (miss) {
+        pw[0] = pw[1] = pw[2] = pw[3] = 0.f;
+      }
+      for (int g0 = 0; g0 < k; g0 += kCG) {
+        const int ng = min(kCG, k - g0);
+        const bool mine = miss && jw >= g0 && jw < g0 + ng;
+        if (!__syncthreads_or(mine)) continue;
+        for (int d0 = 0; d0 < cp; d0 += kDK) {
+          stage_rows<BF>(sh, S, cb, np, C, g0, ng, d0, ld, n, cp, vec, true);
+          __syncthreads();
+          if (mine) stage_direct<BF>(sh, jw - g0, pw);
+          __syncthreads();
+        }
+      }
+    }
     if (valid) {
-      fpart = (double)dist_wide(x, C + (int64_t)jw * cp, n, vec);
+      fpart = (double)((pw[0] + pw[1]) + (pw[2] + pw[3]));
       if (lab) lab[i] = jw;
     }
     fpart = wave_sum_f64(fpart);
@@ -400,11 +604,123 @@ __global__ __launch_bounds__(256, 2) void k_assign_wide(AssignArgs a) {
   }
 }
 
+// Greedy K-means++ potentials for wide points: for every pending candidate
+// c of a job, the new D_i = min(D_i, ||S_i - S_cand_c||^2) into the D slot of
+// that candidate and the sum of every 256-point tile (the four wave sums
+// added in a fixed order).  The tile's rows pass through LDS 32 dimensions at
+// a time with coalesced loads, the candidates' rows sit in LDS whole, and each
+// thread keeps its point's distances in four partial sums by d mod 4 (the
+// dimensions past the last multiple of 4 in the first one), so D is the same
+// as from a thread reading its row directly.
+__global__ __launch_bounds__(256) void k_kpp_pot_wide(KppArgs a) {
+  const int job = a.job_slot ? a.job_slot[blockIdx.y] : (int)blockIdx.y;
+  const KppState ks = a.ks[job];
+  if (ks.ncand == 0) return;
+  const int64_t s = a.s[job];
+  const int64_t base = (int64_t)blockIdx.x * kChunk;
+  if (base >= s) return;
+  const int tid = threadIdx.x;
+  const int64_t i = base + tid;
+  const float* S = a.S + job * a.S_stride;
+  const int n = a.n, cp = a.cp, ld = a.ld, nc = ks.ncand;
+  const int n4 = n & ~3;
+  const int np = (int)min((int64_t)kChunk, s - base);
+  const int vec = (ld % 4 == 0 && (((uintptr_t)S & 15) == 0)) ? 1 : 0;
+  extern __shared__ __align__(16) float kpp_lds[];
+  float* cand = kpp_lds;              // [3][cp]
+  float* rows = kpp_lds + 3 * cp;     // [256][33]
+  __shared__ double red[12];
+  for (int e = tid; e < 3 * cp; e += 256) {  // rows of absent candidates are zero
+    const int c = e / cp, d = e - c * cp;
+    const int64_t row = c == 0 ? ks.cand[0] : (c == 1 ? ks.cand[1] : ks.cand[2]);
+    cand[e] = (c < nc && d < n) ? S[row * ld + d] : 0.f;
+  }
+  const int dslot = ks.dcur;
+  float dcur = 0.f;
+  if (i < s && ks.has_d) dcur = a.D[(int64_t)dslot * a.D_slot_stride + job * a.D_job_stride + i];
+  float p[3][4] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+  for (int d0 = 0; d0 < cp; d0 += kDK) {
+    __syncthreads();
+    {
+      constexpr int kPt = kChunk * (kDK / 4) / 256;
+      float4 v[kPt];
+#pragma unroll
+      for (int u = 0; u < kPt; ++u) {
+        const int e = tid + u * 256, r = e / (kDK / 4), q = e - r * (kDK / 4);
+        v[u] = stage_load(S, base + r, ld, d0 + 4 * q, n, cp, vec, r < np);
+      }
+#pragma unroll
+      for (int u = 0; u < kPt; ++u) {
+        const int e = tid + u * 256, r = e / (kDK / 4), q = e - r * (kDK / 4);
+        float* dst = rows + r * 33 + 4 * q;
+        dst[0] = v[u].x;
+        dst[1] = v[u].y;
+        dst[2] = v[u].z;
+        dst[3] = v[u].w;
+      }
+    }
+    __syncthreads();
+    const int dn = min(kDK, n - d0);  // real dimensions of this stage
+    const float* xr = rows + tid * 33;
+    for (int dd = 0; dd < dn; dd += 4) {
+      const int d = d0 + dd;
+      if (d + 4 <= n4) {
+        const float x0 = xr[dd], x1 = xr[dd + 1], x2 = xr[dd + 2], x3 = xr[dd + 3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const float* cr = cand + c * cp + d;
+          const float u0 = x0 - cr[0], u1 = x1 - cr[1], u2 = x2 - cr[2], u3 = x3 - cr[3];
+          p[c][0] = fmaf(u0, u0, p[c][0]);
+          p[c][1] = fmaf(u1, u1, p[c][1]);
+          p[c][2] = fmaf(u2, u2, p[c][2]);
+          p[c][3] = fmaf(u3, u3, p[c][3]);
+        }
+      } else {  // dimensions past the last multiple of 4, in order, into the first sum
+        const int nq = min(4, dn - dd);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (q < nq) {
+            const float xq = xr[dd + q];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              const float u = xq - cand[c * cp + d + q];
+              p[c][0] = fmaf(u, u, p[c][0]);
+            }
+          }
+        }
+      }
+    }
+  }
+  const int wv = tid >> 6;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if (c < nc) {
+      float m = 0.f;
+      if (i < s) {
+        const float dc = (p[c][0] + p[c][1]) + (p[c][2] + p[c][3]);
+        m = ks.has_d ? kpp_min_nan(dcur, dc) : dc;
+        const int sl = c < dslot ? c : c + 1;
+        a.D[(int64_t)sl * a.D_slot_stride + job * a.D_job_stride + i] = m;
+      }
+      const double part = wave_sum_f64(i < s ? (double)m : 0.0);
+      if ((tid & 63) == 0) red[c * 4 + wv] = part;
+    }
+  }
+  __syncthreads();
+  if (tid == 0)
+    for (int c = 0; c < nc; ++c) {
+      const int sl = c < dslot ? c : c + 1;
+      a.Dt[((int64_t)sl * a.njobs + job) * a.ndt_max + blockIdx.x] =
+          (red[c * 4] + red[c * 4 + 1]) + (red[c * 4 + 2] + red[c * 4 + 3]);
+    }
+}
+
 // Fixed-point sums of the label changes: grid (cp / 64 dimension slices,
 // point ranges of 8,192, jobs).  A point whose label went from jo to jn adds
 // its coordinates to cluster jn and removes them from jo (jo < 0 on the first
-// assignment).  The slice's sums gather in LDS, then go to memory with
-// integer atomics, so the result does not depend on the order.
+// assignment); a wave handles one changed point at a time, one dimension per
+// lane.  The slice's sums gather in LDS, then go to memory with integer
+// atomics, so the result does not depend on the order.
 struct UpdateArgs {
   const float* S;
   int64_t S_stride;
@@ -441,22 +757,37 @@ __global__ __launch_bounds__(256) void k_update_wide(UpdateArgs u) {
   const int32_t* lo = q == 0 ? nullptr : ((q & 1) ? u.lab0 : u.lab1) + job * u.lab_stride;
   const bool counts = blockIdx.x == 0;
   int changed = 0;
-  // one thread per point, the slice's dimensions in order
-  for (int64_t i = r0 + threadIdx.x; i < r1; i += 256) {
-    const int jn = ln[i];
-    const int jo = lo ? lo[i] : -1;
-    if (jn == jo) continue;
-    changed = 1;
-    const float* x = S + i * (int64_t)u.ld + d0;
-    for (int dd = 0; dd < nd; ++dd) {
-      const long long q = quantize(x[dd], u.scale[d0 + dd]);
-      if (q == 0) continue;
-      atomicAdd(&lacc[jn * kUpdDims + dd], (unsigned long long)q);
-      if (jo >= 0) atomicAdd(&lacc[jo * kUpdDims + dd], (unsigned long long)(-q));
+  // each wave reads the labels of 64 consecutive points, then works through
+  // the changed ones together: lane l adds dimension d0 + l of the point
+  // (coalesced row reads, consecutive LDS words)
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const double sc = lane < nd ? u.scale[d0 + lane] : 0.0;
+  for (int64_t i0 = r0 + wv * 64; i0 < r1; i0 += 256) {
+    const int64_t i = i0 + lane;
+    int jn = -1, jo = -1;
+    if (i < r1) {
+      jn = ln[i];
+      jo = lo ? lo[i] : -1;
     }
-    if (counts) {
-      atomicAdd(&lcnt[jn], 1);
-      if (jo >= 0) atomicAdd(&lcnt[jo], -1);
+    unsigned long long pend = __ballot(i < r1 && jn != jo);
+    if (pend) changed = 1;
+    while (pend) {
+      const int src = __ffsll(pend) - 1;
+      pend &= pend - 1;
+      const int pn = __builtin_amdgcn_readlane(jn, src);
+      const int po = __builtin_amdgcn_readlane(jo, src);
+      if (lane < nd) {
+        const float xv = S[(i0 + src) * (int64_t)u.ld + d0 + lane];
+        const long long qv = quantize(xv, sc);
+        if (qv != 0) {
+          atomicAdd(&lacc[pn * kUpdDims + lane], (unsigned long long)qv);
+          if (po >= 0) atomicAdd(&lacc[po * kUpdDims + lane], (unsigned long long)(-qv));
+        }
+      }
+      if (counts && lane == 0) {
+        atomicAdd(&lcnt[pn], 1);
+        if (po >= 0) atomicAdd(&lcnt[po], -1);
+      }
     }
   }
   if (!__syncthreads_or(changed)) return;
@@ -567,6 +898,18 @@ hipError_t launch_assign_wide_bf16(hipStream_t st, const AssignArgs& a, int32_t 
     hipLaunchKernelGGL((k_assign_wide<true, true>), dim3(ntiles), dim3(256), 0, st, a);
   else
     hipLaunchKernelGGL((k_assign_wide<false, true>), dim3(ntiles), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_kpp_pot_wide(hipStream_t st, const KppArgs& a, int32_t njobs, int64_t max_s) {
+  const dim3 grid((unsigned)((max_s + kChunk - 1) / kChunk), (unsigned)njobs);
+  const size_t lds = ((size_t)3 * a.cp + (size_t)kChunk * 33) * sizeof(float);
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_kpp_pot_wide,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_kpp_pot_wide, grid, dim3(256), lds, st, a);
   return hipGetLastError();
 }
 

@@ -94,6 +94,55 @@ def vmf_mixture(per_cluster, n, n_centres, seed=0, kappa=(50.0, 200.0)):
     return np.ascontiguousarray(X[perm])
 
 
+def _vmf_cosines(rng, kappa, p, size):
+    """Cosines w = x.mu of `size` vMF(mu, kappa) points on S^(p-1): Wood's (1994)
+    rejection sampler, vectorised."""
+    b = (p - 1) / (2.0 * kappa + np.sqrt(4.0 * kappa * kappa + (p - 1) ** 2))
+    x0 = (1.0 - b) / (1.0 + b)
+    c = kappa * x0 + (p - 1) * np.log(1.0 - x0 * x0)
+    out = np.empty(size)
+    filled = 0
+    while filled < size:
+        nd = int((size - filled) * 1.25) + 16
+        z = rng.beta((p - 1) / 2.0, (p - 1) / 2.0, nd)
+        u = rng.uniform(size=nd)
+        w = (1.0 - (1.0 + b) * z) / (1.0 - (1.0 - b) * z)
+        ok = kappa * w + (p - 1) * np.log(1.0 - x0 * w) - c >= np.log(u)
+        w = w[ok][: size - filled]
+        out[filled: filled + w.size] = w
+        filled += w.size
+    return out
+
+
+def vmf_mixture_device(per_cluster, n, n_centres, device, seed=0, kappa=(50.0, 200.0)):
+    """The vmf_mixture recipe drawn on a torch device (for sizes the host
+    sampler is too slow for): mean directions and kappa from
+    default_rng(seed), the cosine to the mean direction by Wood's sampler, the
+    tangent direction from a seeded torch generator on the device; points are
+    re-normalised in FP64 and stored FP32, rows shuffled.  Returns an
+    (per_cluster * n_centres) x n float32 tensor on the device."""
+    import torch
+    rng = np.random.default_rng(seed)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    m = per_cluster * n_centres
+    X = torch.empty((m, n), dtype=torch.float32, device=device)
+    for j in range(n_centres):
+        mu = rng.standard_normal(n)
+        mu /= np.linalg.norm(mu)
+        kap = rng.uniform(kappa[0], kappa[1])
+        w = torch.from_numpy(_vmf_cosines(rng, kap, n, per_cluster)).to(device)[:, None]
+        mu_t = torch.from_numpy(mu).to(device)
+        v = torch.randn((per_cluster, n), generator=gen, device=device, dtype=torch.float64)
+        v -= (v @ mu_t)[:, None] * mu_t[None, :]
+        v /= torch.linalg.vector_norm(v, dim=1, keepdim=True)
+        x = w * mu_t[None, :] + torch.sqrt(torch.clamp(1.0 - w * w, min=0.0)) * v
+        x /= torch.linalg.vector_norm(x, dim=1, keepdim=True)
+        X[j * per_cluster: (j + 1) * per_cluster] = x.to(torch.float32)
+    perm = torch.from_numpy(rng.permutation(m)).to(device)
+    return X.index_select(0, perm)
+
+
 # The five workloads (sizes of the configurations this code is measured on).
 WORKLOADS = {
     "blobs2d": dict(desc="20,000 points in 2-D from 5 isotropic Gaussians (centres U[-10,10]^2, "
