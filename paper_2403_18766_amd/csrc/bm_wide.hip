@@ -16,10 +16,10 @@
 // of cp terms), a direct-form re-decision of every point whose best two e are
 // closer than that bound (the whole wave evaluates one such point's centres
 // together; four partial sums by d mod 4), lowest index on ties, and the
-// winner's distance in the direct form sum_d (x_d - c_d)^2, which each thread
-// accumulates from the LDS stages while the rows pass for the matrix cores
-// (for the previous label of its point), or in a second pass when some point
-// of the chunk changed its label.
+// winner's distance in the direct form sum_d (x_d - c_d)^2 (block by block,
+// see stage_total), which each thread accumulates from the LDS stages while
+// the rows pass for the matrix cores (for the previous label of its point),
+// or the whole wave computes for a point whose label changed.
 //
 // Lloyd labels ping-pong between two arrays (assignment q writes array q mod
 // 2), so the update kernel sees the old and the new label of every point.
@@ -165,7 +165,6 @@ struct __align__(16) WideShared {
   float C[kCG * kR];
   double red_f[4];
   int red_i[4];
-  int flag;
 };
 
 // Row of the staging loops: 4 consecutive dimensions d .. d + 3 of row r of
@@ -201,10 +200,8 @@ __device__ inline float4 stage_load(const float* __restrict__ S, int64_t row, in
 }
 
 // One 32-dimension stage of the chunk's rows (256 x 32) and of the centre
-// group g0 (ng rows, zero past k) into LDS, in batches of kBatch float4 per
-// thread whose loads are all issued before their stores.
-constexpr int kBatch = 4;
-
+// group g0 (ng rows, zero past k) into LDS: all loads of the stage are
+// issued before the first store.
 template <bool BF>
 __device__ inline void stage_store(float* dst, const float4 v) {
   if constexpr (BF) {
@@ -224,47 +221,39 @@ __device__ inline void stage_rows(WideShared<BF>& sh, const float* __restrict__ 
   constexpr int R = WideShared<BF>::kR;
   constexpr int kPt = kChunk * (kDK / 4) / 256;  // float4 per thread: rows
   constexpr int kCt = kCG * (kDK / 4) / 256;     // float4 per thread: centres
-  static_assert(kPt % kBatch == 0 && kCt % kBatch == 0, "staging batches");
   const int tid = threadIdx.x;
+  // thread tid takes dimensions d0 + 4 (tid % 8) .. + 3 of rows tid / 8 + 32 u
+  const int r0 = tid / (kDK / 4), q = tid - r0 * (kDK / 4);
+  float4 v[kPt], w[kCt];
 #pragma unroll
-  for (int u0 = 0; u0 < kPt; u0 += kBatch) {
-    float4 v[kBatch];
+  for (int u = 0; u < kPt; ++u)
+    v[u] = stage_load(S, cb + r0 + 32 * u, ld, d0 + 4 * q, n, cp, vec, r0 + 32 * u < np);
+  if (centres) {
 #pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
-      const int e = tid + (u0 + u) * 256, r = e / (kDK / 4), q = e - r * (kDK / 4);
-      v[u] = stage_load(S, cb + r, ld, d0 + 4 * q, n, cp, vec, r < np);
-    }
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
-      const int e = tid + (u0 + u) * 256, r = e / (kDK / 4), q = e - r * (kDK / 4);
-      stage_store<BF>(sh.S + r * R + 4 * q, v[u]);
-    }
+    for (int u = 0; u < kCt; ++u)
+      w[u] = stage_load(C, g0 + r0 + 32 * u, cp, d0 + 4 * q, cp, cp, 1, r0 + 32 * u < ng);
   }
+#pragma unroll
+  for (int u = 0; u < kPt; ++u) stage_store<BF>(sh.S + (r0 + 32 * u) * R + 4 * q, v[u]);
   if (!centres) return;
 #pragma unroll
-  for (int u0 = 0; u0 < kCt; u0 += kBatch) {
-    float4 w[kBatch];
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
-      const int e = tid + (u0 + u) * 256, r = e / (kDK / 4), q = e - r * (kDK / 4);
-      w[u] = stage_load(C, g0 + r, cp, d0 + 4 * q, cp, cp, 1, r < ng);
-    }
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
-      const int e = tid + (u0 + u) * 256, r = e / (kDK / 4), q = e - r * (kDK / 4);
-      stage_store<BF>(sh.C + r * R + 4 * q, w[u]);
-    }
-  }
+  for (int u = 0; u < kCt; ++u) stage_store<BF>(sh.C + (r0 + 32 * u) * R + 4 * q, w[u]);
 }
 
-// Direct-form partial sums of this thread's row (row tid of the stage) against
-// centre row cr of the stage, dimensions in increasing order into p[d mod 4]:
-// over all stages this is the order of dist_wide.
+// The winner's squared distance is defined stage by stage: for every
+// 32-dimension block s (dimensions 32 s .. 32 s + 31 of the padded row) four
+// partial sums by d mod 4 (increasing d, fused multiply-adds) give
+// T_s = (p0 + p1) + (p2 + p3), and the blocks add in order,
+// ((T_0 + T_1) + T_2) + ...  A thread computes T_s of its row against centre
+// row cr while the block sits in LDS (stage_total); a wave computes the whole
+// sum of one point with one block per lane (dist_blocks).  Both give the same
+// bits.
 template <bool BF>
-__device__ inline void stage_direct(const WideShared<BF>& sh, int cr, float (&p)[4]) {
+__device__ inline float stage_total(const WideShared<BF>& sh, int cr) {
   constexpr int R = WideShared<BF>::kR;
   const float* x = sh.S + threadIdx.x * R;
   const float* c = sh.C + cr * R;
+  float p[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int d = 0; d < kDK; d += 4) {
     float xv[4], cv[4];
@@ -286,6 +275,49 @@ __device__ inline void stage_direct(const WideShared<BF>& sh, int cr, float (&p)
       p[q] = fmaf(t, t, p[q]);
     }
   }
+  return (p[0] + p[1]) + (p[2] + p[3]);
+}
+
+// T_s of block s of row x against row c (zero past n, and past cp).
+__device__ inline float block_total(const float* __restrict__ x, const float* __restrict__ c,
+                                    int s, int n, int cp, int vec) {
+  float p[4] = {0.f, 0.f, 0.f, 0.f};
+  const int d0 = s * kDK;
+  if (vec) {
+#pragma unroll
+    for (int g = 0; g < kDK / 4; ++g) {
+      const int d = d0 + 4 * g;
+      if (d < cp) {
+        const float4 a = *reinterpret_cast<const float4*>(x + d);
+        const float4 b = *reinterpret_cast<const float4*>(c + d);
+        const float t0 = a.x - b.x, t1 = a.y - b.y, t2 = a.z - b.z, t3 = a.w - b.w;
+        p[0] = fmaf(t0, t0, p[0]);
+        p[1] = fmaf(t1, t1, p[1]);
+        p[2] = fmaf(t2, t2, p[2]);
+        p[3] = fmaf(t3, t3, p[3]);
+      }
+    }
+  } else {
+    for (int dd = 0; dd < kDK; ++dd) {
+      const int d = d0 + dd;
+      const float t = d < n ? x[d] - c[d] : 0.f;
+      p[dd & 3] = fmaf(t, t, p[dd & 3]);
+    }
+  }
+  return (p[0] + p[1]) + (p[2] + p[3]);
+}
+
+__device__ inline float dist_blocks(const float* __restrict__ x, const float* __restrict__ c, int n,
+                                    int cp, int vec) {
+  const int lane = threadIdx.x & 63;
+  const int nb = (cp + kDK - 1) / kDK;
+  float total = 0.f;
+  for (int s0 = 0; s0 < nb; s0 += 64) {
+    const float t = s0 + lane < nb ? block_total(x, c, s0 + lane, n, cp, vec) : 0.f;
+    const int m = min(64, nb - s0);
+    for (int q = 0; q < m; ++q) total += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t), q));
+  }
+  return total;
 }
 
 // Eight consecutive FP32 values as BF16 high parts and residuals.
@@ -359,7 +391,7 @@ __global__ __launch_bounds__(256, 2) void k_assign_wide(AssignArgs a) {
       pl = prev[i];
       if (pl < 0 || pl >= k) pl = -1;
     }
-    float pw[4] = {0.f, 0.f, 0.f, 0.f};  // direct-form partial sums to pl
+    float wacc = 0.f;  // winner's distance to pl, block by block
     float e1[2], e2[2];
     int j1[2];
     float xxp[2] = {0.f, 0.f};
@@ -383,7 +415,7 @@ __global__ __launch_bounds__(256, 2) void k_assign_wide(AssignArgs a) {
         __syncthreads();  // the previous stage has been consumed
         stage_rows<BF>(sh, S, cb, np, C, g0, ng, d0, ld, n, cp, vec, true);
         __syncthreads();
-        if (mine) stage_direct<BF>(sh, pl - g0, pw);
+        if (mine) wacc += stage_total<BF>(sh, pl - g0);
         if constexpr (!BF) {
           // lane (half, col): A = centre (tile*32 + col) at dim kk + half,
           //                   B = point (wv*64 + b*32 + col) at dim kk + half
@@ -561,31 +593,18 @@ __global__ __launch_bounds__(256, 2) void k_assign_wide(AssignArgs a) {
       }
     }
     }
-    // winner's distance: the accumulated one when the prediction holds, else a
-    // second pass of the rows through LDS for the whole chunk (same order)
-    const bool miss = valid && jw != pl;
-    if (tid == 0) sh.flag = 0;
-    __syncthreads();
-    if (miss) sh.flag = 1;
-    __syncthreads();
-    if (sh.flag) {
-      if (miss) {
-        pw[0] = pw[1] = pw[2] = pw[3] = 0.f;
-      }
-      for (int g0 = 0; g0 < k; g0 += kCG) {
-        const int ng = min(kCG, k - g0);
-        const bool mine = miss && jw >= g0 && jw < g0 + ng;
-        if (!__syncthreads_or(mine)) continue;
-        for (int d0 = 0; d0 < cp; d0 += kDK) {
-          stage_rows<BF>(sh, S, cb, np, C, g0, ng, d0, ld, n, cp, vec, true);
-          __syncthreads();
-          if (mine) stage_direct<BF>(sh, jw - g0, pw);
-          __syncthreads();
-        }
-      }
+    // winner's distance: the accumulated one when the prediction holds, else
+    // the whole wave computes it for each such point (same bits)
+    unsigned long long missed = __ballot(valid && jw != pl);
+    while (missed) {
+      const int src = __ffsll(missed) - 1;
+      missed &= missed - 1;
+      const int jq = __builtin_amdgcn_readlane(jw, src);
+      const float dq = dist_blocks(S + (cb + wv * 64 + src) * (int64_t)ld, C + (int64_t)jq * cp, n, cp, vec);
+      if (lane == src) wacc = dq;
     }
     if (valid) {
-      fpart = (double)((pw[0] + pw[1]) + (pw[2] + pw[3]));
+      fpart = (double)wacc;
       if (lab) lab[i] = jw;
     }
     fpart = wave_sum_f64(fpart);
