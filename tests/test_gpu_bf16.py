@@ -185,3 +185,25 @@ def test_serve_bf16_alone_equals_mix(dev, api):
     key = lambda res: [(q["f"], q["f_incumbent"], q["iters"], q["accepted"], q["ndeg"]) for q in res]
     assert st["peak_running"] > 1
     assert key(mix) == key(alone)
+
+
+@pytest.mark.parametrize("prec", [0, BF16])
+def test_nonfinite_inputs_wide(dev, api, prec):
+    # NaN or infinity in a point: the objective is reported non-finite and a
+    # Lloyd run stops at once (its f cannot decrease)
+    r = np.random.default_rng(9)
+    X = r.standard_normal((600, 96)).astype(np.float32)
+    C = X[:5].copy()
+    for bad in (np.nan, np.inf):
+        Y = X.copy()
+        Y[311, 40] = bad
+        say("non-finite wide", prec, bad)
+        f, _, _ = api.objective(to_dev(Y, dev), to_dev(C, dev), prec=prec)
+        assert not math.isfinite(f)
+        res = api.lloyd(to_dev(Y, dev), to_dev(C, dev), prec=prec)
+        assert not math.isfinite(res["f"]) and res["iters"] == 0
+    # finite data far beyond BF16's exact range still gives the FP32 path's result
+    Z = (X * 3e4).astype(np.float32)
+    fz, lz, _ = api.objective(to_dev(Z, dev), to_dev(Z[:5].copy(), dev), prec=prec)
+    f32, l32, _ = api.objective(to_dev(Z, dev), to_dev(Z[:5].copy(), dev))
+    assert abs(fz - f32) <= F_TOL * f32

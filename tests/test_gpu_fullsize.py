@@ -1,0 +1,110 @@
+"""GPU parity at the full sizes of the measured workloads, in the launch
+configurations bench.py times (fewer rounds, same per-launch shapes), checked
+on outputs the FP64 oracle can compute: f(C_best, X) over every point, and
+the labels of sampled points.
+
+  * vmf768: 2,000,000 unit vectors in 768-D, k = 100, 16 workers with samples
+    of 131,072 (one launch per Lloyd step), FP32 and BF16 matrix cores;
+  * noisy28: 10,000,000 points in 28-D, k = 50, 64 workers with BINS sizes in
+    [2^12, 2^17] (one persistent launch per round);
+  * serving: the three resident 4,000,000-point data sets (n = 16, 64, 256)
+    with a slice of the job stream; each result is the same served alone.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import kmeans as okm
+from paper_2403_18766_amd import datagen
+from tests.gpu_common import require_gpu, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+F_TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2403_18766_amd import api as a
+    return a
+
+
+def _check_run(X_host, g, label, rng):
+    C = g["C_best"].cpu().numpy()
+    Y = g["Y"].cpu().numpy()
+    rows = np.sort(rng.choice(X_host.shape[0], 20_000, replace=False))
+    olab, _, _, onear = okm.assign(X_host[rows], C, return_second=True)
+    mism = np.count_nonzero(Y[rows][~onear] != olab[~onear])
+    assert mism == 0, f"{label}: {mism} sampled labels differ outside near ties"
+    say(label, "oracle f over all", X_host.shape[0], "points")
+    fo = okm.objective(X_host, C)
+    assert abs(g["f_full"] - fo) <= F_TOL * fo, (label, g["f_full"], fo)
+    return fo
+
+
+def test_vmf768_full_size_both_precisions(dev, api):
+    say("vmf768 full size: generating 2,000,000 x 768 on the device")
+    X = datagen.vmf_mixture_device(20_000, 768, 100, dev, seed=0)
+    P = dict(k=100, workers=16, rounds_T=1, passes_p=2, s_min=131_072, s_max=131_072,
+             size_policy=1, seed=0, batched=2)
+    runs = {}
+    for prec in (0, 1):
+        say("vmf768 full size: run, prec", prec)
+        runs[prec] = api.bigmeans_run(X, api.RunParams(prec=prec, **P))
+    Xh = X.cpu().numpy()
+    del X
+    rng = np.random.default_rng(0)
+    fo = _check_run(Xh, runs[0], "vmf768 fp32", rng)
+    if np.array_equal(runs[1]["C_best"].cpu().numpy(), runs[0]["C_best"].cpu().numpy()):
+        assert runs[1]["f_full"] == runs[0]["f_full"]
+    else:
+        _check_run(Xh, runs[1], "vmf768 bf16", rng)
+    assert abs(runs[1]["f_full"] - fo) <= 0.01 * fo
+
+
+def test_noisy28_full_size_persistent_rounds(dev, api):
+    from paper_2403_18766_amd import _lib
+    say("noisy28 full size: generating 10,000,000 x 28")
+    Xh = datagen.make("noisy28")
+    X = to_dev(Xh, dev)
+    P = api.RunParams(k=50, workers=64, rounds_T=3, passes_p=10, s_min=1 << 12, s_max=1 << 17,
+                      size_policy=_lib.BM_SIZE_BINS, seed=0, batched=1)
+    say("noisy28 full size: run")
+    g = api.bigmeans_run(X, P)
+    assert 1 << 12 <= g["s_opt"] <= 1 << 17
+    _check_run(Xh, g, "noisy28", np.random.default_rng(1))
+    # the same run in one launch per Lloyd step gives the same bits
+    say("noisy28 full size: run, one launch per Lloyd step")
+    P.batched = 2
+    g2 = api.bigmeans_run(X, P)
+    assert g2["f_full"] == g["f_full"]
+    assert np.array_equal(g2["C_best"].cpu().numpy(), g["C_best"].cpu().numpy())
+
+
+def test_serving_full_size_datasets_alone_equals_mix(dev, api):
+    say("serving full size: generating three 4,000,000-point data sets")
+    Xs = [to_dev(datagen.serving_dataset(n, m=4_000_000), dev) for n in (16, 64, 256)]
+    r = np.random.default_rng(0)
+    jobs = []
+    for _ in range(60):
+        s = int(math.floor(math.exp(r.uniform(math.log(1024), math.log(262_145)))))
+        jobs.append(dict(s=min(s, 262_144), dataset=int(r.integers(3)), k=int(r.choice([10, 50, 200])),
+                         worker=int(r.integers(4)), prec=int(r.integers(2))))
+    say("serving full size: mix")
+    mix, st = api.serve(Xs, jobs, seed=0, max_slots=64)
+    say("serving full size: alone")
+    alone, _ = api.serve(Xs, jobs, seed=0, max_slots=1)
+    key = lambda res: [(q["f"], q["f_incumbent"], q["iters"], q["accepted"], q["ndeg"]) for q in res]
+    assert st["peak_running"] > 1
+    assert key(mix) == key(alone)
+    for q in mix:
+        assert math.isfinite(q["f"])
+        if q["accepted"]:
+            assert q["f_incumbent"] == q["f"]
