@@ -40,6 +40,7 @@ constexpr size_t kStageBytes = 256 * 1024;
 constexpr int kNBins = 5;
 constexpr int kMaxDim = 4096;            // largest point dimension
 constexpr size_t kMaxLds = 160 * 1024;   // LDS of one compute unit
+constexpr int kStagedKppDim = 32;        // rows this wide: K-means++ potentials staged through LDS
 
 int round_up4(int n) { return (n + 3) & ~3; }
 
@@ -620,8 +621,8 @@ int kpp_batch(bm_ctx* c, const BatchView& b, const KppBatch& kb) {
   HIP_TRY(c, bm::launch_kpp_init(c->stream, a, J, smax));
   for (int step = 0; step < kb.steps; ++step) {
     HIP_TRY(c, bm::launch_kpp_step(c->stream, a, J));
-    if (cp > bm::kMaxRegDim)
-      HIP_TRY(c, bm::launch_kpp_pot_wide(c->stream, a, J, smax));
+    if (cp >= kStagedKppDim)
+      HIP_TRY(c, bm::launch_kpp_pot_staged(c->stream, a, J, smax));
     else
       HIP_TRY(c, bm::launch_kpp_pot(c->stream, a, J, smax));
   }
@@ -1147,8 +1148,8 @@ int serve_admit(bm_ctx* c, ServeState& st, std::vector<ServeWorker>& workers,
     HIP_TRY(c, bm::launch_kpp_init(str, a, A, smax));
     for (int step = 0; step < steps; ++step) {
       HIP_TRY(c, bm::launch_kpp_step(str, a, A));
-      if (a.cp > bm::kMaxRegDim)
-        HIP_TRY(c, bm::launch_kpp_pot_wide(str, a, A, smax));
+      if (a.cp >= kStagedKppDim)
+        HIP_TRY(c, bm::launch_kpp_pot_staged(str, a, A, smax));
       else
         HIP_TRY(c, bm::launch_kpp_pot(str, a, A, smax));
     }

@@ -1,6 +1,6 @@
-// Declarations of wide-point kernels of bm_wide.hip that bm_kernels.hip does
-// not share (matrix-core precisions, staged K-means++ potentials); the
-// argument structures are in bm_internal.h.
+// Declarations of kernels of bm_wide.hip that bm_kernels.hip does not share
+// (matrix-core precisions, staged K-means++ potentials); the argument
+// structures are in bm_internal.h.
 #pragma once
 
 #include <stdint.h>
@@ -18,8 +18,9 @@ namespace bm {
 // tile_pts must be a multiple of 256.
 hipError_t launch_assign_wide_bf16(hipStream_t st, const AssignArgs& a, int32_t ntiles, bool sums);
 
-// K-means++ potentials for wide points (same results as launch_kpp_pot, with
-// the rows staged through LDS by coalesced loads).
-hipError_t launch_kpp_pot_wide(hipStream_t st, const KppArgs& a, int32_t njobs, int64_t max_s);
+// K-means++ potentials with the rows staged through LDS by coalesced loads
+// (same results as launch_kpp_pot; the faster one for rows of 32 floats or
+// more).
+hipError_t launch_kpp_pot_staged(hipStream_t st, const KppArgs& a, int32_t njobs, int64_t max_s);
 
 }  // namespace bm

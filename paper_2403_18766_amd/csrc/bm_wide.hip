@@ -623,7 +623,7 @@ __global__ __launch_bounds__(256, 2) void k_assign_wide(AssignArgs a) {
   }
 }
 
-// Greedy K-means++ potentials for wide points: for every pending candidate
+// Greedy K-means++ potentials, rows staged through LDS: for every pending candidate
 // c of a job, the new D_i = min(D_i, ||S_i - S_cand_c||^2) into the D slot of
 // that candidate and the sum of every 256-point tile (the four wave sums
 // added in a fixed order).  The tile's rows pass through LDS 32 dimensions at
@@ -631,7 +631,7 @@ __global__ __launch_bounds__(256, 2) void k_assign_wide(AssignArgs a) {
 // thread keeps its point's distances in four partial sums by d mod 4 (the
 // dimensions past the last multiple of 4 in the first one), so D is the same
 // as from a thread reading its row directly.
-__global__ __launch_bounds__(256) void k_kpp_pot_wide(KppArgs a) {
+__global__ __launch_bounds__(256) void k_kpp_pot_staged(KppArgs a) {
   const int job = a.job_slot ? a.job_slot[blockIdx.y] : (int)blockIdx.y;
   const KppState ks = a.ks[job];
   if (ks.ncand == 0) return;
@@ -920,15 +920,15 @@ hipError_t launch_assign_wide_bf16(hipStream_t st, const AssignArgs& a, int32_t 
   return hipGetLastError();
 }
 
-hipError_t launch_kpp_pot_wide(hipStream_t st, const KppArgs& a, int32_t njobs, int64_t max_s) {
+hipError_t launch_kpp_pot_staged(hipStream_t st, const KppArgs& a, int32_t njobs, int64_t max_s) {
   const dim3 grid((unsigned)((max_s + kChunk - 1) / kChunk), (unsigned)njobs);
   const size_t lds = ((size_t)3 * a.cp + (size_t)kChunk * 33) * sizeof(float);
   if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_kpp_pot_wide,
+    hipError_t e = hipFuncSetAttribute((const void*)k_kpp_pot_staged,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_kpp_pot_wide, grid, dim3(256), lds, st, a);
+  hipLaunchKernelGGL(k_kpp_pot_staged, grid, dim3(256), lds, st, a);
   return hipGetLastError();
 }
 
