@@ -982,6 +982,7 @@ int validate_params(bm_ctx* c, const bm_params* p) {
 // ---------------------------------------------------------------------------
 struct ServeWorker {
   int d = 0, k = 0, w = 0;
+  int store_group = -1;  // group whose stream last wrote this worker's incumbent
   uint32_t rng_worker = 0;
   int64_t off_c = 0, off_deg = 0;  // offsets in the incumbent store
   double fhat = std::numeric_limits<double>::infinity();
@@ -1003,6 +1004,8 @@ struct ServeGroup {
   std::vector<int64_t> sizes;  // its sample size, 0 when free
   LloydSetup L;
   int running = 0;
+  hipStream_t stream = nullptr;   // the group's own stream (groups run concurrently)
+  hipEvent_t store_ev = nullptr;  // recorded after the group's latest incumbent writes
 };
 
 // Device bytes one running job of sample size s uses (sample, indices, two
@@ -1018,8 +1021,11 @@ struct ServeState {
   float* store_c = nullptr;
   uint8_t* store_deg = nullptr;
   ~ServeState() {
-    for (ServeGroup& g : groups)
-      if (g.c) bm_destroy(g.c);
+    for (ServeGroup& g : groups) {
+      if (g.c) bm_destroy(g.c);  // synchronises the group's stream
+      if (g.store_ev) (void)hipEventDestroy(g.store_ev);
+      if (g.stream) (void)hipStreamDestroy(g.stream);
+    }
     if (store_c) (void)hipFree(store_c);
     if (store_deg) (void)hipFree(store_deg);
   }
@@ -1051,6 +1057,8 @@ int serve_admit(bm_ctx* c, ServeState& st, std::vector<ServeWorker>& workers,
   for (const auto& jq : adm) {
     const ServeWorker& W = workers[job_worker[jq.first]];
     const int q = jq.second;
+    if (W.store_group >= 0 && st.groups[W.store_group].stream != str)
+      HIP_TRY(c, hipStreamWaitEvent(str, st.groups[W.store_group].store_ev, 0));
     HIP_TRY(c, hipMemcpyAsync(P<float>(gc->Cinc) + (int64_t)q * k * n, st.store_c + W.off_c,
                               (size_t)k * n * sizeof(float), hipMemcpyDeviceToDevice, str));
     HIP_TRY(c, hipMemcpyAsync(P<uint8_t>(gc->deg_inc) + (int64_t)q * k, st.store_deg + W.off_deg,
@@ -1232,7 +1240,9 @@ int serve_impl(bm_ctx* c, const bm_dataset* ds, int nds, const bm_job* jobs, int
   HIP_TRY(c, hipMemsetAsync(st.store_deg, 1, (size_t)ndg, c->stream));
   // one context per (dataset, k): workspace for its slots, data scales, idle job states
   for (ServeGroup& G : st.groups) {
-    int rc = bm_create(c->device, c->stream, &G.c);
+    HIP_TRY(c, hipStreamCreateWithFlags(&G.stream, hipStreamNonBlocking));
+    HIP_TRY(c, hipEventCreateWithFlags(&G.store_ev, hipEventDisableTiming));
+    int rc = bm_create(c->device, G.stream, &G.c);
     if (rc != BM_OK) return c->fail(rc, "serving workspace: context creation failed");
     rc = reserve_impl(G.c, G.s_max, G.n, G.k, G.slots);
     if (rc != BM_OK) return c->fail(rc, "serving workspace: %s", G.c->err.c_str());
@@ -1335,10 +1345,12 @@ int serve_impl(bm_ctx* c, const bm_dataset* ds, int nds, const bm_job* jobs, int
     }
     ++steps;
     // finished jobs leave; an accepted result becomes the worker's incumbent
-    for (ServeGroup& G : st.groups) {
+    for (size_t gi = 0; gi < st.groups.size(); ++gi) {
+      ServeGroup& G = st.groups[gi];
       if (G.running == 0) continue;
       hs.resize(G.slots);
       BM_TRY(readback(G.c, G.L.js, G.slots * sizeof(JobState), hs.data()));
+      bool wrote = false;
       for (int q = 0; q < G.slots; ++q) {
         const int j = G.slot_job[q];
         if (j < 0 || hs[q].active) continue;
@@ -1351,9 +1363,11 @@ int serve_impl(bm_ctx* c, const bm_dataset* ds, int nds, const bm_job* jobs, int
         if (hs[q].accepted) {
           HIP_TRY(c, hipMemcpyAsync(st.store_c + W.off_c, P<float>(G.c->Cinc) + (int64_t)q * G.k * G.n,
                                     (size_t)G.k * G.n * sizeof(float), hipMemcpyDeviceToDevice,
-                                    c->stream));
+                                    G.stream));
           HIP_TRY(c, hipMemcpyAsync(st.store_deg + W.off_deg, P<uint8_t>(G.c->deg_inc) + (int64_t)q * G.k,
-                                    (size_t)G.k, hipMemcpyDeviceToDevice, c->stream));
+                                    (size_t)G.k, hipMemcpyDeviceToDevice, G.stream));
+          W.store_group = (int)gi;
+          wrote = true;
           W.fhat = hs[q].f;
           W.ndeg = hs[q].ndeg;
         }
@@ -1369,8 +1383,10 @@ int serve_impl(bm_ctx* c, const bm_dataset* ds, int nds, const bm_job* jobs, int
         inflight -= serve_job_bytes(jobs[j].s, G.n, G.k);
         ++done;
       }
+      if (wrote) HIP_TRY(c, hipEventRecord(G.store_ev, G.stream));
     }
   }
+  for (ServeGroup& G : st.groups) HIP_TRY(c, hipStreamSynchronize(G.stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   if (stats) {
     stats->seconds = elapsed();
