@@ -207,3 +207,17 @@ def test_nonfinite_inputs_wide(dev, api, prec):
     fz, lz, _ = api.objective(to_dev(Z, dev), to_dev(Z[:5].copy(), dev), prec=prec)
     f32, l32, _ = api.objective(to_dev(Z, dev), to_dev(Z[:5].copy(), dev))
     assert abs(fz - f32) <= F_TOL * f32
+
+
+def test_precision_argument_is_checked(dev, api):
+    from paper_2403_18766_amd.api import BigmeansError
+    X = to_dev(np.ones((100, 70), np.float32), dev)
+    with pytest.raises(BigmeansError):
+        api.objective(X, X[:3].clone(), prec=2)
+    with pytest.raises(BigmeansError):
+        api.lloyd(X, X[:3].clone(), prec=-1)
+    # a narrow data set accepts BF16 and runs the FP32 vector path (same bits)
+    Y = to_dev(np.random.default_rng(0).standard_normal((500, 12)).astype(np.float32), dev)
+    a = api.objective(Y, Y[:4].clone(), prec=BF16)
+    b = api.objective(Y, Y[:4].clone())
+    assert a[0] == b[0] and np.array_equal(a[1].cpu().numpy(), b[1].cpu().numpy())
