@@ -421,3 +421,18 @@ def test_bigmeans_trace_and_nan_rows(dev, api):
     assert g["improvements"] == 0
     assert [r for r, _ in seen] == [0, 1]
     assert all(math.isinf(f) for _, fh in seen for f in fh)
+
+
+@pytest.mark.parametrize("n", [36, 64])
+def test_bigmeans_modes_identical_wider_rows(dev, api, n):
+    # rows of 32 floats or more: outside the round kernel the K-means++
+    # potentials stage the rows through LDS; every mode still gives the same bits
+    X = datagen.noisy_mixture(30_000, n, 10, seed=n)
+    P = dict(k=12, workers=4, rounds_T=2, passes_p=3, s_min=1500, s_max=5000, seed=3,
+             size_policy=2)
+    say("bigmeans modes, n =", n)
+    runs = [api.bigmeans_run(to_dev(X, dev), api.RunParams(batched=b, **P)) for b in (1, 2, 0)]
+    a = runs[0]
+    for b in runs[1:]:
+        assert a["f_full"] == b["f_full"] and a["lloyd_dists"] == b["lloyd_dists"]
+        assert np.array_equal(a["C_best"].cpu().numpy(), b["C_best"].cpu().numpy())
