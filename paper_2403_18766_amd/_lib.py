@@ -99,6 +99,7 @@ SIGNATURES = [
                             ct.c_int32, ct.POINTER(ServeParams), ct.POINTER(JobResult),
                             ct.POINTER(ServeStats)]),
     ("bm_set_profiling", ct.c_int, [ct.c_void_p, ct.c_int]),
+    ("bm_set_tuning", ct.c_int, [ct.c_void_p, ct.c_int]),
     ("bm_get_stats", ct.c_int, [ct.c_void_p, ct.POINTER(Stats)]),
     ("bm_philox4x64", None, [ct.POINTER(ct.c_uint64), ct.POINTER(ct.c_uint64),
                              ct.POINTER(ct.c_uint64)]),

@@ -219,6 +219,14 @@ def set_profiling(device, on=True):
     _check(lib, c, lib.bm_set_profiling(c, 1 if on else 0))
 
 
+def set_tuning(device, on=True):
+    """bm_set_tuning on the context of (device, current stream): tile-size timing
+    of the one-step-per-launch Lloyd paths on or off (kept choices cleared)."""
+    device = torch.device(device)
+    lib, c = _ctx(device)
+    _check(lib, c, lib.bm_set_tuning(c, 1 if on else 0))
+
+
 def get_stats(device):
     """bm_get_stats: dict of the Lloyd kernel timing counters."""
     device = torch.device(device)

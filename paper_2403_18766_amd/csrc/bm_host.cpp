@@ -80,10 +80,15 @@ struct bm_ctx {
   size_t rb_bytes = 0;
 
   hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
+  hipEvent_t tev0 = nullptr, tev1 = nullptr;  // tile tuning
 
   // profiling of the Lloyd kernels (bm_set_profiling)
   bool prof = false;
-  std::vector<hipEvent_t> pev;  // 3 events per iteration: before assign, after assign, after finalize
+  std::vector<hipEvent_t> pev;
+  // tile sizes chosen by timing (key: padded dimension, k, log2 of the
+  // batch's points); bm_set_tuning switches the timing off
+  bool tune = true;
+  std::map<uint64_t, int> tuned_tile;  // 3 events per iteration: before assign, after assign, after finalize
   bm_stats stats{};
 
   int fail(int code, const char* fmt, ...) {
@@ -322,6 +327,77 @@ struct BatchView {
   std::vector<int64_t> sizes;
 };
 
+// Points per assignment workgroup for a batch: the first batch of each
+// (padded dimension, k, log2 points) times one assignment launch per
+// candidate — the heuristic's choice, half and twice it — in objective mode
+// (no labels, sums or job state touched; only the chunk partials, which the
+// next assignment rewrites) and keeps the fastest.  The batch's sizes, centroids
+// and norms must be on the device.  Results do not depend on the choice (every
+// reduction is per 256-point chunk, in a fixed order).
+int tuned_tile_pts(bm_ctx* c, const BatchView& b, const std::vector<int64_t>& sizes, int* out) {
+  const int base = choose_tile_pts(sizes);
+  *out = base;
+  int64_t total = 0;
+  for (int64_t v : sizes) total += v;
+  if (!c->tune || total < 4 * 1024) return BM_OK;
+  int lg = 0;
+  while ((int64_t)1 << (lg + 1) <= total) ++lg;
+  const uint64_t key = ((uint64_t)b.cp << 40) | ((uint64_t)b.k << 16) | (uint64_t)lg;
+  auto it = c->tuned_tile.find(key);
+  if (it != c->tuned_tile.end()) {
+    *out = it->second;
+    return BM_OK;
+  }
+  std::vector<int> cands;
+  for (int t : {base / 2, base, base * 2})
+    if (t >= 2 * bm::kWG && t % (2 * bm::kWG) == 0) cands.push_back(t);
+  if (!c->tev0) {
+    HIP_TRY(c, hipEventCreate(&c->tev0));
+    HIP_TRY(c, hipEventCreate(&c->tev1));
+  }
+  bm::AssignArgs a{};
+  a.S = b.S;
+  a.S_stride = b.S_stride;
+  a.ld = b.ld;
+  a.n = b.n;
+  a.cp = b.cp;
+  a.k = b.k;
+  a.max_chunks = (int32_t)c->max_chunks;
+  a.vec = (b.ld == b.cp && aligned16(b.S) && (b.S_stride % 4) == 0) ? 1 : 0;
+  a.s = P<int64_t>(c->sizes) + b.first;
+  a.Cp = P<float>(c->Cp) + (int64_t)b.first * b.k * b.cp;
+  a.C_stride = (int64_t)b.k * b.cp;
+  a.cn = P<float>(c->cn) + (int64_t)b.first * b.k;
+  a.cn_stride = b.k;
+  a.tf = P<double>(c->tf) + (int64_t)b.first * c->max_chunks;
+  const bool wide = b.cp > bm::kMaxRegDim;
+  float best_ms = 0.f;
+  for (int t : cands) {
+    TileMap tm = make_tiles(sizes, t);
+    BM_TRY(upload_tiles(c, tm));
+    a.tile_pts = t;
+    a.tile_job = P<int32_t>(c->tile_job);
+    a.tile_idx = P<int32_t>(c->tile_idx);
+    float ms = 0.f;
+    for (int rep = 0; rep < 2; ++rep) {  // the first launch warms the caches
+      HIP_TRY(c, hipEventRecord(c->tev0, c->stream));
+      if (wide)
+        HIP_TRY(c, bm::launch_assign_wide(c->stream, a, tm.total, false));
+      else
+        HIP_TRY(c, bm::launch_assign(c->stream, a, tm.total, false));
+      HIP_TRY(c, hipEventRecord(c->tev1, c->stream));
+      HIP_TRY(c, hipEventSynchronize(c->tev1));
+      HIP_TRY(c, hipEventElapsedTime(&ms, c->tev0, c->tev1));
+    }
+    if (t == cands.front() || ms < best_ms) {
+      best_ms = ms;
+      *out = t;
+    }
+  }
+  c->tuned_tile[key] = *out;
+  return BM_OK;
+}
+
 // Kernel arguments of Lloyd iterations over the jobs (slots) of a batch.
 struct LloydSetup {
   bm::AssignArgs a{};
@@ -457,12 +533,14 @@ int lloyd_batch(bm_ctx* c, const BatchView& b, int max_iter, double tol, int32_t
   const int J = b.njobs, first = b.first, k = b.k, cp = b.cp;
   LloydSetup L;
   BM_TRY(lloyd_setup(c, b, max_iter, tol, labels, lab_stride, accept, &L, prec));
-  TileMap tm = make_tiles(b.sizes, choose_tile_pts(b.sizes));
-  BM_TRY(upload_tiles(c, tm));
   BM_TRY(upload(c, P<int64_t>(c->sizes) + first, b.sizes.data(), J * sizeof(int64_t)));
   HIP_TRY(c, bm::launch_job_init(c->stream, L.js, P<int64_t>(c->sizes) + first, J, k, cp, L.acc,
                                  L.cnt, P<float>(c->Cp) + (int64_t)first * k * cp,
                                  P<float>(c->cn) + (int64_t)first * k));
+  int tp = 0;
+  BM_TRY(tuned_tile_pts(c, b, b.sizes, &tp));  // after the norms: timing launches read them
+  TileMap tm = make_tiles(b.sizes, tp);
+  BM_TRY(upload_tiles(c, tm));
   int64_t max_size = 0;
   for (int64_t v : b.sizes) max_size = std::max(max_size, v);
 
@@ -524,7 +602,8 @@ int lloyd_batch(bm_ctx* c, const BatchView& b, int max_iter, double tol, int32_t
     if (launched >= max_iter + 1) return c->fail(BM_E_STATE, "Lloyd did not stop after %d steps", launched);
     if (shrink) {
       // fewer points left: smaller tiles spread them over more compute units
-      tm = make_tiles(live, choose_tile_pts(live));
+      BM_TRY(tuned_tile_pts(c, b, live, &tp));
+      tm = make_tiles(live, tp);
       BM_TRY(upload_tiles(c, tm));
     }
     chunk = std::min(chunk * 2, 16);
@@ -1328,9 +1407,6 @@ int serve_impl(bm_ctx* c, const bm_dataset* ds, int nds, const bm_job* jobs, int
     // one Lloyd iteration of every running job
     for (ServeGroup& G : st.groups) {
       if (G.running == 0) continue;
-      TileMap tm = make_tiles(G.sizes, choose_tile_pts(G.sizes));
-      BM_TRY(upload_tiles(G.c, tm));
-      BM_TRY(upload(G.c, P<int64_t>(G.c->sizes), G.sizes.data(), G.slots * sizeof(int64_t)));
       BatchView b;
       b.first = 0;
       b.njobs = G.slots;
@@ -1341,6 +1417,11 @@ int serve_impl(bm_ctx* c, const bm_dataset* ds, int nds, const bm_job* jobs, int
       b.S_stride = G.c->max_s * G.cp;
       b.ld = G.cp;
       b.sizes = G.sizes;
+      BM_TRY(upload(G.c, P<int64_t>(G.c->sizes), G.sizes.data(), G.slots * sizeof(int64_t)));
+      int tp = 0;
+      BM_TRY(tuned_tile_pts(G.c, b, G.sizes, &tp));
+      TileMap tm = make_tiles(G.sizes, tp);
+      BM_TRY(upload_tiles(G.c, tm));
       BM_TRY(lloyd_launch(G.c, G.L, b, tm, G.s_max, -1));
     }
     ++steps;
@@ -1459,6 +1540,8 @@ BM_API void bm_destroy(bm_ctx* c) {
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   if (c->ev2) (void)hipEventDestroy(c->ev2);
+  if (c->tev0) (void)hipEventDestroy(c->tev0);
+  if (c->tev1) (void)hipEventDestroy(c->tev1);
   for (hipEvent_t e : c->pev) (void)hipEventDestroy(e);
   delete c;
 }
@@ -1620,6 +1703,13 @@ BM_API int bm_set_profiling(bm_ctx* c, int on) {
   if (!c) return BM_E_ARG;
   c->prof = on != 0;
   c->stats = bm_stats{};
+  return BM_OK;
+}
+
+BM_API int bm_set_tuning(bm_ctx* c, int on) {
+  if (!c) return BM_E_ARG;
+  c->tune = on != 0;
+  c->tuned_tile.clear();
   return BM_OK;
 }
 

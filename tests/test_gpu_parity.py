@@ -436,3 +436,28 @@ def test_bigmeans_modes_identical_wider_rows(dev, api, n):
     for b in runs[1:]:
         assert a["f_full"] == b["f_full"] and a["lloyd_dists"] == b["lloyd_dists"]
         assert np.array_equal(a["C_best"].cpu().numpy(), b["C_best"].cpu().numpy())
+
+
+def test_tile_tuning_changes_no_result(dev, api):
+    # the tile size of the one-step-per-launch Lloyd paths is chosen by timing;
+    # every choice gives the same bits (narrow and wide points, Algorithm 1)
+    r = np.random.default_rng(21)
+    out = {}
+    for on in (False, True):
+        api.set_tuning(dev, on)
+        res = []
+        for n, k in ((20, 17), (96, 40)):
+            S = (r.standard_normal((60_000, n)) + 3 * r.integers(0, 8, (60_000, 1))).astype(np.float32) \
+                if on is False else out["S", n]
+            out["S", n] = S
+            C0 = S[:k].copy()
+            g = api.lloyd(to_dev(S, dev), to_dev(C0, dev))
+            res.append((g["f"], g["iters"], g["C"].cpu().numpy().tobytes(), g["labels"].cpu().numpy().tobytes()))
+        X = _data("aniso28", 80_000, 4)
+        b = api.bigmeans_run(to_dev(X, dev), api.RunParams(k=25, workers=6, rounds_T=2, passes_p=2,
+                                                           s_min=4096, s_max=30_000, size_policy=2,
+                                                           seed=2, batched=2))
+        res.append((b["f_full"], b["C_best"].cpu().numpy().tobytes()))
+        out[on] = res
+    api.set_tuning(dev, True)
+    assert out[False] == out[True]
