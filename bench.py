@@ -191,6 +191,26 @@ def precision_run(torch, dev):
     return out
 
 
+def mode_comparison(torch, api, Xd, P, ms_mode1, f_mode1):
+    """The same Algorithm-1 step with one launch per Lloyd step (mode 2) and one
+    worker's sample per launch (mode 0, the plain per-sample GPU path): the
+    batched mode's speed-up at equal results (the modes give the same bits)."""
+    import dataclasses
+    out = {}
+    for name, mode in (("one_launch_per_lloyd_step", 2), ("one_worker_per_launch", 0)):
+        Pm = dataclasses.replace(P, batched=mode)
+        api.bigmeans_run(Xd, Pm, labels=False)  # warm-up (tile-size tuning)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = api.bigmeans_run(Xd, Pm, labels=False)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0)
+        out[name] = {"ms_per_step": ms, "f_full": r["f_full"], "same_f_bits": r["f_full"] == f_mode1,
+                     "speedup_of_persistent_rounds": ms / ms_mode1}
+        log("mode", mode, "ms", ms, "f_full", r["f_full"])
+    return out
+
+
 def reference_f(X):
     from paper_2403_18766_amd import datagen
     path = os.path.join(ROOT, "tests", "golden", f"{WORKLOAD['name']}_reference.json")
@@ -215,6 +235,8 @@ def main():
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-target run")
     ap.add_argument("--serve-jobs", type=int, default=2000,
                     help="jobs of the serving measurement (0 skips it)")
+    ap.add_argument("--no-modes", action="store_true",
+                    help="skip the comparison with the multi-launch and plain per-sample modes")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the FP32 / BF16 matrix-core measurement")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -295,6 +317,9 @@ def main():
                 ttt = {"seconds": t + final_stage, "round": rnd, "f": best, "f_oracle": f_ref}
                 break
 
+    modes = None
+    if not args.no_modes and args.mode == 1:
+        modes = mode_comparison(torch, api, Xd, P, 1e3 * wall / args.steps, results[-1]["f_full"])
     cpu = None if args.no_cpu else cpu_baseline(X, args.cpu_workers, args.cpu_passes)
     del Xd
     serving = serve_run(torch, dev, args.serve_jobs) if args.serve_jobs > 0 else None
@@ -321,6 +346,7 @@ def main():
         "p99_latency_ms": serving["p99_latency_ms"] if serving else None,
         "serving": serving,
         "precision": precision,
+        "modes": modes,
     }
     print(json.dumps(out), flush=True)
 
