@@ -1099,12 +1099,14 @@ struct ServeState {
   std::vector<ServeGroup> groups;
   float* store_c = nullptr;
   uint8_t* store_deg = nullptr;
+  hipEvent_t start_ev = nullptr;
   ~ServeState() {
     for (ServeGroup& g : groups) {
       if (g.c) bm_destroy(g.c);  // synchronises the group's stream
       if (g.store_ev) (void)hipEventDestroy(g.store_ev);
       if (g.stream) (void)hipStreamDestroy(g.stream);
     }
+    if (start_ev) (void)hipEventDestroy(start_ev);
     if (store_c) (void)hipFree(store_c);
     if (store_deg) (void)hipFree(store_deg);
   }
@@ -1317,10 +1319,16 @@ int serve_impl(bm_ctx* c, const bm_dataset* ds, int nds, const bm_job* jobs, int
   HIP_TRY(c, hipMalloc(&st.store_deg, (size_t)ndg));
   HIP_TRY(c, hipMemsetAsync(st.store_c, 0, (size_t)nc * sizeof(float), c->stream));
   HIP_TRY(c, hipMemsetAsync(st.store_deg, 1, (size_t)ndg, c->stream));
-  // one context per (dataset, k): workspace for its slots, data scales, idle job states
+  // the groups' streams start after the caller's stream: the data sets it
+  // produced and the store initialised above
+  HIP_TRY(c, hipEventCreateWithFlags(&st.start_ev, hipEventDisableTiming));
+  HIP_TRY(c, hipEventRecord(st.start_ev, c->stream));
+  // one context per (dataset, k, precision): workspace for its slots, data
+  // scales, idle job states
   for (ServeGroup& G : st.groups) {
     HIP_TRY(c, hipStreamCreateWithFlags(&G.stream, hipStreamNonBlocking));
     HIP_TRY(c, hipEventCreateWithFlags(&G.store_ev, hipEventDisableTiming));
+    HIP_TRY(c, hipStreamWaitEvent(G.stream, st.start_ev, 0));
     int rc = bm_create(c->device, G.stream, &G.c);
     if (rc != BM_OK) return c->fail(rc, "serving workspace: context creation failed");
     rc = reserve_impl(G.c, G.s_max, G.n, G.k, G.slots);
