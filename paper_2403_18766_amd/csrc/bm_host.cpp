@@ -84,11 +84,11 @@ struct bm_ctx {
 
   // profiling of the Lloyd kernels (bm_set_profiling)
   bool prof = false;
-  std::vector<hipEvent_t> pev;
+  std::vector<hipEvent_t> pev;  // 3 events per iteration: before assign, after assign, after finalize
   // tile sizes chosen by timing (key: padded dimension, k, log2 of the
   // batch's points); bm_set_tuning switches the timing off
   bool tune = true;
-  std::map<uint64_t, int> tuned_tile;  // 3 events per iteration: before assign, after assign, after finalize
+  std::map<uint64_t, int> tuned_tile;
   bm_stats stats{};
 
   int fail(int code, const char* fmt, ...) {
@@ -656,6 +656,47 @@ int objective_batch(bm_ctx* c, const BatchView& b, int32_t* labels, int64_t lab_
   return BM_OK;
 }
 
+// K-means++ initial D of wide points on the matrix cores: jobs (slots
+// base..base+J-1 of the workspace) with sizes `sizes` (0: no tiles), whose
+// working centroids and flags are in place (launch_kpp_init_wide).
+int kpp_init_wide(bm_ctx* c, hipStream_t st, const bm::KppArgs& ka, int base, int J,
+                  const std::vector<int64_t>& sizes) {
+  const int k = ka.k, cp = ka.cp;
+  float* cn = P<float>(c->cn) + (int64_t)base * k;
+  // norms of the working centroids (the same values the Lloyd kernels keep)
+  HIP_TRY(c, bm::launch_centroid_norms(st, ka.Cp, cp, k, J, cn));
+  TileMap tm = make_tiles(sizes, choose_tile_pts(sizes));
+  if (tm.total == 0) return BM_OK;
+  BM_TRY(upload_tiles(c, tm));
+  bm::AssignArgs a{};
+  a.S = ka.S;
+  a.S_stride = ka.S_stride;
+  a.ld = ka.ld;
+  a.n = ka.n;
+  a.cp = cp;
+  a.k = k;
+  a.tile_pts = tm.tile_pts;
+  a.max_chunks = (int32_t)c->max_chunks;
+  a.vec = (ka.ld == cp && aligned16(ka.S) && (ka.S_stride % 4) == 0) ? 1 : 0;
+  a.s = ka.s;
+  a.tile_job = P<int32_t>(c->tile_job);
+  a.tile_idx = P<int32_t>(c->tile_idx);
+  a.Cp = ka.Cp;
+  a.C_stride = ka.C_stride;
+  a.cn = cn;
+  a.cn_stride = k;
+  a.tf = P<double>(c->tf);
+  bm::KppInitOut kp{};
+  kp.ks = ka.ks;
+  kp.deg = ka.deg;
+  kp.D = ka.D;  // slot 0 of the D buffers
+  kp.D_job_stride = ka.D_job_stride;
+  kp.Dt = ka.Dt;
+  kp.Dt_job_stride = ka.ndt_max;
+  HIP_TRY(c, bm::launch_kpp_init_wide(st, a, tm.total, kp));
+  return BM_OK;
+}
+
 struct KppBatch {
   const uint64_t* seed_worker_host;  // [J][2]
   uint64_t g;
@@ -697,7 +738,10 @@ int kpp_batch(bm_ctx* c, const BatchView& b, const KppBatch& kb) {
   a.g = kb.g;
   a.n_cand = kb.n_cand;
   HIP_TRY(c, bm::launch_kpp_setup(c->stream, a, J));
-  HIP_TRY(c, bm::launch_kpp_init(c->stream, a, J, smax));
+  if (cp > bm::kMaxRegDim)
+    BM_TRY(kpp_init_wide(c, c->stream, a, first, J, b.sizes));
+  else
+    HIP_TRY(c, bm::launch_kpp_init(c->stream, a, J, smax));
   for (int step = 0; step < kb.steps; ++step) {
     HIP_TRY(c, bm::launch_kpp_step(c->stream, a, J));
     if (cp >= kStagedKppDim)
@@ -1234,7 +1278,10 @@ int serve_admit(bm_ctx* c, ServeState& st, std::vector<ServeWorker>& workers,
     a.n_cand = sp.n_candidates;
     a.job_slot = P<int32_t>(gc->rflags);
     HIP_TRY(c, bm::launch_kpp_setup(str, a, A));
-    HIP_TRY(c, bm::launch_kpp_init(str, a, A, smax));
+    if (cp > bm::kMaxRegDim)
+      BM_TRY(kpp_init_wide(gc, str, a, 0, J, sz));
+    else
+      HIP_TRY(c, bm::launch_kpp_init(str, a, A, smax));
     for (int step = 0; step < steps; ++step) {
       HIP_TRY(c, bm::launch_kpp_step(str, a, A));
       if (a.cp >= kStagedKppDim)

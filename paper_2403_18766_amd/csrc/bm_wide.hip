@@ -336,10 +336,16 @@ __device__ inline void split8(const float* v, bf16x8& h, bf16x8& l) {
   }
 }
 
-template <bool SUMS, bool BF>
-__global__ __launch_bounds__(256, 2) void k_assign_wide(AssignArgs a) {
+template <bool SUMS, bool BF, bool KPP>
+__global__ __launch_bounds__(256, 2) void k_assign_wide(AssignArgs a, KppInitOut kp) {
   constexpr int R = WideShared<BF>::kR;
   const int job = a.tile_job[blockIdx.x];
+  const uint8_t* dg = nullptr;  // K-means++ initial D: centroids to leave out
+  if (KPP) {
+    const KppState kst = kp.ks[job];
+    if (kst.ntodo == 0 || !kst.has_d) return;
+    dg = kp.deg + (int64_t)job * a.k;
+  }
   int parity = 0, iter = 0;
   if (a.st) {
     const JobState st = a.st[job];
@@ -370,7 +376,8 @@ __global__ __launch_bounds__(256, 2) void k_assign_wide(AssignArgs a) {
   const int half = lane >> 5, col = lane & 31;
 
   float cmax2 = 0.f;
-  for (int j = lane; j < k; j += 64) cmax2 = fmaxf(cmax2, cn[j]);
+  for (int j = lane; j < k; j += 64)
+    if (!KPP || !dg[j]) cmax2 = fmaxf(cmax2, cn[j]);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) cmax2 = fmaxf(cmax2, __shfl_xor(cmax2, off, 64));
   const float cmax = sqrtf(cmax2) * 1.0000002f;
@@ -472,7 +479,7 @@ __global__ __launch_bounds__(256, 2) void k_assign_wide(AssignArgs a) {
 #pragma unroll
           for (int v = 0; v < 16; ++v) {
             const int c = g0 + t * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
-            if (c < k) {
+            if (c < k && (!KPP || !dg[c])) {
               const float e = fmaf(-2.f, acc[b][t][v], cn[c]);
               e2[b] = __builtin_amdgcn_fmed3f(e1[b], e, e2[b]);
               j1[b] = e < e1[b] ? c : j1[b];
@@ -522,7 +529,7 @@ __global__ __launch_bounds__(256, 2) void k_assign_wide(AssignArgs a) {
 #pragma unroll
           for (int v = 0; v < 16; ++v) {
             const int c = t * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
-            if (c < k) {
+            if (c < k && (!KPP || !dg[c])) {
               const float e = fmaf(-2.f, acc[b][t][v], cn[c]);
               if (!((e - E1) > 2.f * Bb + 2.5e-5f * fabsf(e + XX))) m |= 1ull << (t * 16 + v);
             }
@@ -571,6 +578,7 @@ __global__ __launch_bounds__(256, 2) void k_assign_wide(AssignArgs a) {
       float b1 = __builtin_inff(), b2 = __builtin_inff();
       int jb = 0;
       for (int j = lane; j < k; j += 64) {
+        if (KPP && dg[j]) continue;
         const float dd = dist_wide(xs, C + (int64_t)j * cp, n, vec);
         if (dd < b1) {
           b2 = b1;
@@ -606,6 +614,7 @@ __global__ __launch_bounds__(256, 2) void k_assign_wide(AssignArgs a) {
     if (valid) {
       fpart = (double)wacc;
       if (lab) lab[i] = jw;
+      if (KPP) kp.D[(int64_t)job * kp.D_job_stride + i] = wacc;
     }
     fpart = wave_sum_f64(fpart);
     if (lane == 0) sh.red_f[wv] = fpart;
@@ -615,7 +624,11 @@ __global__ __launch_bounds__(256, 2) void k_assign_wide(AssignArgs a) {
     }
     __syncthreads();
     if (tid == 0) {
-      tfj[cb / kChunk] = (sh.red_f[0] + sh.red_f[1]) + (sh.red_f[2] + sh.red_f[3]);
+      const double tot = (sh.red_f[0] + sh.red_f[1]) + (sh.red_f[2] + sh.red_f[3]);
+      if (KPP)
+        kp.Dt[(int64_t)job * kp.Dt_job_stride + cb / kChunk] = tot;
+      else
+        tfj[cb / kChunk] = tot;
       if (want_near)
         a.tnear[(int64_t)job * a.max_chunks + cb / kChunk] =
             (sh.red_i[0] + sh.red_i[1]) + (sh.red_i[2] + sh.red_i[3]);
@@ -904,19 +917,28 @@ __global__ __launch_bounds__(256) void k_finalize_wide(FinalizeArgs a) {
 // ---------------------------------------------------------------------------
 hipError_t launch_assign_wide(hipStream_t st, const AssignArgs& a, int32_t ntiles, bool sums) {
   if (a.tile_pts % kChunk != 0) return hipErrorInvalidValue;
+  const KppInitOut none{};
   if (sums)
-    hipLaunchKernelGGL((k_assign_wide<true, false>), dim3(ntiles), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_assign_wide<true, false, false>), dim3(ntiles), dim3(256), 0, st, a, none);
   else
-    hipLaunchKernelGGL((k_assign_wide<false, false>), dim3(ntiles), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_assign_wide<false, false, false>), dim3(ntiles), dim3(256), 0, st, a, none);
   return hipGetLastError();
 }
 
 hipError_t launch_assign_wide_bf16(hipStream_t st, const AssignArgs& a, int32_t ntiles, bool sums) {
   if (a.tile_pts % kChunk != 0) return hipErrorInvalidValue;
+  const KppInitOut none{};
   if (sums)
-    hipLaunchKernelGGL((k_assign_wide<true, true>), dim3(ntiles), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_assign_wide<true, true, false>), dim3(ntiles), dim3(256), 0, st, a, none);
   else
-    hipLaunchKernelGGL((k_assign_wide<false, true>), dim3(ntiles), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_assign_wide<false, true, false>), dim3(ntiles), dim3(256), 0, st, a, none);
+  return hipGetLastError();
+}
+
+hipError_t launch_kpp_init_wide(hipStream_t st, const AssignArgs& a, int32_t ntiles,
+                                const KppInitOut& kp) {
+  if (a.tile_pts % kChunk != 0 || a.labels || a.st || a.tnear) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_assign_wide<false, false, true>), dim3(ntiles), dim3(256), 0, st, a, kp);
   return hipGetLastError();
 }
 

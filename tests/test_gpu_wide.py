@@ -160,6 +160,31 @@ def test_kmeanspp_wide_valid(dev, api):
     assert fg <= 1.5 * fo
 
 
+@pytest.mark.parametrize("n,m,k,seed", [(768, 4_000, 20, 3), (100, 3_001, 37, 5), (200, 777, 130, 6)])
+def test_kmeanspp_wide_partial_reseed(dev, api, n, m, k, seed):
+    # kept centroids near sample points, the rest reseeded: the initial D over
+    # the kept ones comes from the matrix-core assignment (k = 130 takes the
+    # lane-per-centre recheck, m = 777 a ragged last tile)
+    from tests.test_gpu_parity import _replay_kmeanspp
+    r = np.random.default_rng(seed)
+    S = (r.standard_normal((m, n)) + 3.0 * r.standard_normal((8, n))[r.integers(8, size=m)]).astype(np.float32)
+    C = (S[r.choice(m, k, replace=False)] + 0.1 * r.standard_normal((k, n))).astype(np.float32)
+    deg = (r.random(k) < 0.4).astype(np.uint8)
+    deg[0] = 1
+    deg[1] = 0
+    say("kmeans++ wide partial", S.shape, k, int(deg.sum()))
+    Cg, dg, picks = api.seed(to_dev(S, dev), to_dev(C, dev), to_dev(deg, dev), 3, seed=seed,
+                             worker=1, g=7, return_picks=True)
+    Cg = Cg.cpu().numpy()
+    picks = picks.cpu().numpy()
+    keep = deg == 0
+    assert dg.cpu().numpy().sum() == 0
+    assert np.array_equal(Cg[keep], C[keep])
+    assert np.array_equal(Cg[~keep], S[picks[~keep, 0]])
+    exact, steps = _replay_kmeanspp(S, C, deg.astype(bool), picks, 3, seed, 1, 7)
+    assert steps == deg.sum() and exact >= steps - 1
+
+
 def test_bigmeans_wide_end_to_end_and_modes(dev, api):
     # 768-D unit vectors, k = 10, 4 workers of 2,000 points, 2 rounds x 3 passes
     X = datagen.make("vmf768", m=20_000, seed=4)
