@@ -221,7 +221,8 @@ def set_profiling(device, on=True):
 
 def set_tuning(device, on=True):
     """bm_set_tuning on the context of (device, current stream): tile-size timing
-    of the one-step-per-launch Lloyd paths on or off (kept choices cleared)."""
+    of the one-step-per-launch Lloyd paths on or off (kept choices cleared;
+    serving always takes the heuristic tile size)."""
     device = torch.device(device)
     lib, c = _ctx(device)
     _check(lib, c, lib.bm_set_tuning(c, 1 if on else 0))

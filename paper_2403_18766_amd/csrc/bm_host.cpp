@@ -1378,12 +1378,15 @@ int serve_impl(bm_ctx* c, const bm_dataset* ds, int nds, const bm_job* jobs, int
     HIP_TRY(c, hipStreamWaitEvent(G.stream, st.start_ev, 0));
     int rc = bm_create(c->device, G.stream, &G.c);
     if (rc != BM_OK) return c->fail(rc, "serving workspace: context creation failed");
+    // no tile-size timing: it waits for the group's stream, which would stall
+    // the host loop that feeds every group
+    G.c->tune = false;
     rc = reserve_impl(G.c, G.s_max, G.n, G.k, G.slots);
     if (rc != BM_OK) return c->fail(rc, "serving workspace: %s", G.c->err.c_str());
     const bm_dataset& D = ds[G.d];
     rc = compute_scales(G.c, D.X, D.m, D.n, D.n, G.cp, G.s_max);
     if (rc != BM_OK) return c->fail(rc, "%s", G.c->err.c_str());
-    HIP_TRY(c, hipMemsetAsync(G.c->js.p, 0, (size_t)G.slots * sizeof(JobState), c->stream));
+    HIP_TRY(c, hipMemsetAsync(G.c->js.p, 0, (size_t)G.slots * sizeof(JobState), G.stream));
     G.slot_job.assign(G.slots, -1);
     G.sizes.assign(G.slots, 0);
     BatchView b;
