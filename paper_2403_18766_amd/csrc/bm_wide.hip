@@ -15,7 +15,8 @@
 // 2 x.c_j, a rigorous bound on its FP32 rounding error (any summation order
 // of cp terms), a direct-form re-decision of every point whose best two e are
 // closer than that bound (the whole wave evaluates one such point's centres
-// together; four partial sums by d mod 4), lowest index on ties, and the
+// together; for k <= 256 only the centres inside the bound's band, marked
+// in per-lane masks), lowest index on ties, and the
 // winner's distance in the direct form sum_d (x_d - c_d)^2 (block by block,
 // see stage_total), which each thread accumulates from the LDS stages while
 // the rows pass for the matrix cores (for the previous label of its point),
@@ -165,6 +166,9 @@ struct __align__(16) WideShared {
   float C[kCG * kR];
   double red_f[4];
   int red_i[4];
+  // candidate masks of the first centre group when there are two groups
+  // ([wave][point block][lane], lane layout of the matrix-core results)
+  unsigned long long m0[4][2][64];
 };
 
 // Row of the staging loops: 4 consecutive dimensions d .. d + 3 of row r of
@@ -336,7 +340,7 @@ __device__ inline void split8(const float* v, bf16x8& h, bf16x8& l) {
   }
 }
 
-template <bool SUMS, bool BF, bool KPP>
+template <bool SUMS, bool BF, bool KPP, bool G2>
 __global__ __launch_bounds__(256, 2) void k_assign_wide(AssignArgs a, KppInitOut kp) {
   constexpr int R = WideShared<BF>::kR;
   const int job = a.tile_job[blockIdx.x];
@@ -357,6 +361,9 @@ __global__ __launch_bounds__(256, 2) void k_assign_wide(AssignArgs a, KppInitOut
   const int64_t t0 = (int64_t)a.tile_idx[blockIdx.x] * a.tile_pts;
   const int64_t t1 = min(s, t0 + (int64_t)a.tile_pts);
   const int k = a.k, n = a.n, cp = a.cp, ld = a.ld;
+  // two centre groups, both re-decided through candidate masks (G2 builds
+  // only: the masks of the first group take registers the others keep)
+  const bool two = G2 && k > kCG && k <= 2 * kCG;
   const float* __restrict__ S = a.S + job * a.S_stride;
   const float* __restrict__ C = a.Cp + job * a.C_stride;
   const float* __restrict__ cn = a.cn + job * a.cn_stride;
@@ -488,6 +495,30 @@ __global__ __launch_bounds__(256, 2) void k_assign_wide(AssignArgs a, KppInitOut
           }
         }
       }
+      if (two && g0 == 0) {
+        // candidates of the first group against the running best: a later
+        // group can only lower the best, so these masks (with a 0.1 % wider
+        // band) hold every centre of the group that the final band admits
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const float XX = xxp[b] + __shfl_xor(xxp[b], 32, 64);
+          const float E1 = fminf(e1[b], __shfl_xor(e1[b], 32, 64));
+          const float Bb = kB * (sqrtf(XX) * cmax + cmax2);
+          unsigned long long m = 0ull;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+              const int c = t * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
+              if (!KPP || !dg[c]) {
+                const float e = fmaf(-2.f, acc[b][t][v], cn[c]);
+                if (!((e - E1) > (2.f * Bb + 2.5e-5f * fabsf(e + XX)) * 1.001f)) m |= 1ull << (t * 16 + v);
+              }
+            }
+          }
+          sh.m0[wv][b][lane] = m;
+        }
+      }
     }
     // combine the two halves of every point's centre set
 #pragma unroll
@@ -508,14 +539,17 @@ __global__ __launch_bounds__(256, 2) void k_assign_wide(AssignArgs a, KppInitOut
     const float B = kB * (sqrtf(xx) * cmax + cmax2);
     const bool recheck = valid && !((pe2 - pe1) > 2.f * B + 2.5e-5f * fabsf(pe2 + xx));
     int jw = pj1;
-    if (k <= kCG) {
+    if (k <= kCG || two) {
       // Re-decision among the candidates only: a centre j whose e_j exceeds
       // the point's best e by more than 2 B + 2.5e-5 |e_j + ||x||^2| is
       // certified farther than the winner and not within the near-tie band.
       // Lane (half, col) marks, for point col of each block, the candidates
-      // among its centres (bit 16 t + v for centre 32 t + 8 (v / 4) + 4 half
-      // + v % 4); then the wave takes the flagged points one at a time and
-      // their candidates one at a time (lanes over the dimensions).
+      // among its centres of the last group (bit 16 t + v for centre
+      // gl + 32 t + 8 (v / 4) + 4 half + v % 4; the first group's masks, if
+      // there are two groups, are in LDS); then the wave takes the flagged
+      // points one at a time and their candidates one at a time (lanes over
+      // the dimensions).
+      const int gl = two ? kCG : 0;
       unsigned long long cmask[2];
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
@@ -528,7 +562,7 @@ __global__ __launch_bounds__(256, 2) void k_assign_wide(AssignArgs a, KppInitOut
         for (int t = 0; t < 4; ++t) {
 #pragma unroll
           for (int v = 0; v < 16; ++v) {
-            const int c = t * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
+            const int c = gl + t * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
             if (c < k && (!KPP || !dg[c])) {
               const float e = fmaf(-2.f, acc[b][t][v], cn[c]);
               if (!((e - E1) > 2.f * Bb + 2.5e-5f * fabsf(e + XX))) m |= 1ull << (t * 16 + v);
@@ -551,12 +585,14 @@ __global__ __launch_bounds__(256, 2) void k_assign_wide(AssignArgs a, KppInitOut
         const float* xs = S + (cb + wv * 64 + src) * (int64_t)ld;
         float b1 = __builtin_inff(), b2 = __builtin_inff();
         int jb = 0;
-        for (int h = 0; h < 2; ++h) {
-          unsigned long long mm = mh[h];
+        for (int q = two ? 0 : 2; q < 4; ++q) {
+          const int h = q & 1;
+          unsigned long long mm = q < 2 ? sh.m0[wv][sb][sc + 32 * h] : mh[h];
+          const int go = q < 2 ? 0 : gl;
           while (mm) {
             const int bit = __ffsll(mm) - 1;
             mm &= mm - 1;
-            const int c = (bit >> 4) * 32 + 8 * ((bit & 15) >> 2) + 4 * h + (bit & 3);
+            const int c = go + (bit >> 4) * 32 + 8 * ((bit & 15) >> 2) + 4 * h + (bit & 3);
             const float dd = dist_wave(xs, C + (int64_t)c * cp, n, cp, vec);
             top2_merge(b1, jb, b2, dd, c, __builtin_inff());
           }
@@ -918,27 +954,37 @@ __global__ __launch_bounds__(256) void k_finalize_wide(FinalizeArgs a) {
 hipError_t launch_assign_wide(hipStream_t st, const AssignArgs& a, int32_t ntiles, bool sums) {
   if (a.tile_pts % kChunk != 0) return hipErrorInvalidValue;
   const KppInitOut none{};
-  if (sums)
-    hipLaunchKernelGGL((k_assign_wide<true, false, false>), dim3(ntiles), dim3(256), 0, st, a, none);
+  const bool g2 = a.k > kCG && a.k <= 2 * kCG;
+  if (sums && g2)
+    hipLaunchKernelGGL((k_assign_wide<true, false, false, true>), dim3(ntiles), dim3(256), 0, st, a, none);
+  else if (sums)
+    hipLaunchKernelGGL((k_assign_wide<true, false, false, false>), dim3(ntiles), dim3(256), 0, st, a, none);
+  else if (g2)
+    hipLaunchKernelGGL((k_assign_wide<false, false, false, true>), dim3(ntiles), dim3(256), 0, st, a, none);
   else
-    hipLaunchKernelGGL((k_assign_wide<false, false, false>), dim3(ntiles), dim3(256), 0, st, a, none);
+    hipLaunchKernelGGL((k_assign_wide<false, false, false, false>), dim3(ntiles), dim3(256), 0, st, a, none);
   return hipGetLastError();
 }
 
+// (one BF16 build serves every k: its register allocation with the two-group
+// masks was measured no slower at k <= 128)
 hipError_t launch_assign_wide_bf16(hipStream_t st, const AssignArgs& a, int32_t ntiles, bool sums) {
   if (a.tile_pts % kChunk != 0) return hipErrorInvalidValue;
   const KppInitOut none{};
   if (sums)
-    hipLaunchKernelGGL((k_assign_wide<true, true, false>), dim3(ntiles), dim3(256), 0, st, a, none);
+    hipLaunchKernelGGL((k_assign_wide<true, true, false, true>), dim3(ntiles), dim3(256), 0, st, a, none);
   else
-    hipLaunchKernelGGL((k_assign_wide<false, true, false>), dim3(ntiles), dim3(256), 0, st, a, none);
+    hipLaunchKernelGGL((k_assign_wide<false, true, false, true>), dim3(ntiles), dim3(256), 0, st, a, none);
   return hipGetLastError();
 }
 
 hipError_t launch_kpp_init_wide(hipStream_t st, const AssignArgs& a, int32_t ntiles,
                                 const KppInitOut& kp) {
   if (a.tile_pts % kChunk != 0 || a.labels || a.st || a.tnear) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_assign_wide<false, false, true>), dim3(ntiles), dim3(256), 0, st, a, kp);
+  if (a.k > kCG && a.k <= 2 * kCG)
+    hipLaunchKernelGGL((k_assign_wide<false, false, true, true>), dim3(ntiles), dim3(256), 0, st, a, kp);
+  else
+    hipLaunchKernelGGL((k_assign_wide<false, false, true, false>), dim3(ntiles), dim3(256), 0, st, a, kp);
   return hipGetLastError();
 }
 

@@ -69,6 +69,18 @@ def test_objective_wide_shapes(dev, api, m, n, k):
     _check_objective(api, dev, X, C, f"m={m} n={n} k={k}")
 
 
+@pytest.mark.parametrize("k", [129, 200, 256, 257])
+def test_objective_wide_two_groups_many_redecisions(dev, api, k):
+    # noisy 256-D mixture, centres near data points: most points have several
+    # centres of their own cluster at nearly the same distance, so a large
+    # share goes through the re-decision -- among the candidates of
+    # both centre groups up to k = 256, among all centres above
+    X = datagen.serving_dataset(256, m=6_000, seed=3)
+    r = np.random.default_rng(k)
+    C = (X[r.choice(len(X), k, replace=False)] + 0.05 * r.standard_normal((k, 256))).astype(np.float32)
+    _check_objective(api, dev, X, C, f"two groups k={k}")
+
+
 def test_objective_wide_far_from_origin(dev, api):
     # large ||x|| and ||c||: most points go through the direct-form re-decision
     r = np.random.default_rng(1)
