@@ -92,6 +92,22 @@ __device__ inline float dist_direct_mem(const float* __restrict__ x, const float
   return (p0 + p1) + (p2 + p3);
 }
 
+// dist_direct_reg with the point's row in LDS (same operation order).
+template <int NP>
+__device__ inline float dist_direct_lds(const float* x, const float* __restrict__ c) {
+  float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
+#pragma unroll
+  for (int d = 0; d < NP; d += 4) {
+    const float t0 = x[d] - c[d], t1 = x[d + 1] - c[d + 1];
+    const float t2 = x[d + 2] - c[d + 2], t3 = x[d + 3] - c[d + 3];
+    p0 = fmaf(t0, t0, p0);
+    p1 = fmaf(t1, t1, p1);
+    p2 = fmaf(t2, t2, p2);
+    p3 = fmaf(t3, t3, p3);
+  }
+  return (p0 + p1) + (p2 + p3);
+}
+
 template <int NP>
 __device__ inline float dist_direct_reg(const float (&x)[NP], const float* __restrict__ c) {
   float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
@@ -273,7 +289,7 @@ typedef const double __attribute__((address_space(4)))* cdouble_p;
 // by the previous kernel, so per-centroid fetches from memory would leave
 // every wave waiting on a chain of cache misses); the distance loop then
 // reads each centroid row as LDS broadcasts and feeds it to PPL*NP FMAs.
-template <int NP, int PPL, bool SUMS>
+template <int NP, int PPL, bool SUMS, bool COOP = false>
 __device__ inline void assign_range(const AssignArgs& a, int job, int64_t p_begin, int64_t p_end,
                                     int first_assign, unsigned char* smem, bool staged = false,
                                     double* tfj = nullptr, unsigned long long* accj = nullptr,
@@ -404,7 +420,62 @@ __device__ inline void assign_range(const AssignArgs& a, int job, int64_t p_begi
       const float B = kB * (sqrtf(xx) * cmax + cmax2);
       const bool recheck = valid[p] && !((e2[p] - e1[p]) > 2.f * B + 2.5e-5f * fabsf(e2[p] + xx));
       int jw = j1[p];
-      if (recheck) {
+      if constexpr (COOP) {
+        // the wave re-decides its flagged points one at a time: the point's
+        // row goes to LDS, lane l ranks the centres l, l + 64, ... and the
+        // lanes' best two merge (lowest index on equal distances) -- the
+        // same values and choice as one lane ranking all centres in order
+        __shared__ float xrow[kWG / 64][NP];
+        const int lane = threadIdx.x & 63;
+        unsigned long long pending = __ballot(recheck);
+        while (pending) {
+          const int src = __ffsll(pending) - 1;
+          pending &= pending - 1;
+          if (lane == src) {
+#pragma unroll
+            for (int d = 0; d < NP; ++d) xrow[wv][d] = x[p][d];
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          float b1 = __builtin_inff(), b2 = __builtin_inff();
+          int jb = 0;
+          for (int j = lane; j < k; j += 64) {
+            // the row is read from LDS for every centre rather than held in
+            // registers (the kernel's registers already hold its points)
+            __asm__ volatile("" ::: "memory");
+            const float dd = dist_direct_lds<NP>(xrow[wv], sC + j * NP);
+            if (dd < b1) {
+              b2 = b1;
+              b1 = dd;
+              jb = j;
+            } else if (dd < b2) {
+              b2 = dd;
+            }
+          }
+#pragma unroll
+          for (int off = 32; off > 0; off >>= 1) {
+            const float o1 = __shfl_xor(b1, off, 64);
+            const int oj = __shfl_xor(jb, off, 64);
+            const float o2 = __shfl_xor(b2, off, 64);
+            if (o1 < b1 || (o1 == b1 && oj < jb)) {
+              b2 = fminf(b1, o2);
+              b1 = o1;
+              jb = oj;
+            } else {
+              b2 = fminf(b2, o1);
+            }
+          }
+          if (lane == src) {
+            jw = jb;
+            if (b2 - b1 < 1e-5f * b2) ++near;
+          }
+          // every lane has read the row before the next point replaces it
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+      } else if (recheck) {
         float b1 = __builtin_inff(), b2 = __builtin_inff();
         int jb = 0;
         for (int j = 0; j < k; ++j) {
@@ -491,7 +562,7 @@ __device__ inline void assign_range(const AssignArgs& a, int job, int64_t p_begi
 }
 
 // Multi-launch form: one workgroup per tile of the flattened tile map.
-template <int NP, int PPL, bool SUMS>
+template <int NP, int PPL, bool SUMS, bool COOP>
 __global__ __launch_bounds__(kWG) void k_assign_small(AssignArgs a) {
   const int job = a.tile_job[blockIdx.x];
   const int t = a.tile_idx[blockIdx.x];
@@ -505,7 +576,7 @@ __global__ __launch_bounds__(kWG) void k_assign_small(AssignArgs a) {
   const int64_t p_begin = (int64_t)t * a.tile_pts;
   const int64_t p_end = min(s, p_begin + a.tile_pts);
   extern __shared__ __align__(16) unsigned char smem[];
-  assign_range<NP, PPL, SUMS>(a, job, p_begin, p_end, first_assign, smem);
+  assign_range<NP, PPL, SUMS, COOP>(a, job, p_begin, p_end, first_assign, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -1510,29 +1581,33 @@ hipError_t launch_round_np(hipStream_t st, const RoundArgs* r_dev, int grid, siz
                                     (unsigned int)lds, st);
 }
 
-template <int NP>
-hipError_t launch_assign_np(hipStream_t st, const AssignArgs& a, int ntiles, bool sums) {
+template <int NP, bool SUMS, bool COOP>
+hipError_t launch_assign_v(hipStream_t st, const AssignArgs& a, int ntiles, size_t lds) {
   // two points per lane while both fit comfortably in registers
   constexpr int PPL = NP <= 32 ? 2 : 1;
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_assign_small<NP, PPL, SUMS, COOP>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((k_assign_small<NP, PPL, SUMS, COOP>), dim3(ntiles), dim3(kWG), lds, st, a);
+  return hipGetLastError();
+}
+
+// From 64 centres on, the wave re-decides its flagged points together (the
+// sequential form costs k distances per lane whenever one lane of the wave
+// needs it); below, the sequential form keeps the kernel's registers lower.
+template <int NP>
+hipError_t launch_assign_np(hipStream_t st, const AssignArgs& a, int ntiles, bool sums) {
   const size_t base = (((size_t)a.k * NP + a.k) * 4 + 15) / 16 * 16;
+  const bool coop = a.k >= 64;
   if (sums) {
     const size_t lds = base + (size_t)a.k * NP * 8 + (size_t)a.k * 4;
-    if (lds > 64 * 1024) {
-      hipError_t e = hipFuncSetAttribute((const void*)k_assign_small<NP, PPL, true>,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL((k_assign_small<NP, PPL, true>), dim3(ntiles), dim3(kWG), lds, st, a);
-  } else {
-    const size_t lds = base;
-    if (lds > 64 * 1024) {
-      hipError_t e = hipFuncSetAttribute((const void*)k_assign_small<NP, PPL, false>,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL((k_assign_small<NP, PPL, false>), dim3(ntiles), dim3(kWG), lds, st, a);
+    return coop ? launch_assign_v<NP, true, true>(st, a, ntiles, lds)
+                : launch_assign_v<NP, true, false>(st, a, ntiles, lds);
   }
-  return hipGetLastError();
+  return coop ? launch_assign_v<NP, false, true>(st, a, ntiles, base)
+              : launch_assign_v<NP, false, false>(st, a, ntiles, base);
 }
 
 }  // namespace

@@ -102,6 +102,17 @@ def test_objective_shapes(dev, api, m, n, k):
     _check_objective(api, dev, X, C, f"shape m={m} n={n} k={k}")
 
 
+@pytest.mark.parametrize("n,k", [(64, 63), (64, 64), (64, 200), (28, 100), (8, 300)])
+def test_objective_narrow_many_redecisions(dev, api, n, k):
+    # noisy mixture with centres near data points: many points have several
+    # centres of their own cluster at nearly the same distance; from k = 64 on
+    # the wave re-decides its flagged points together (lanes over centres)
+    X = datagen.serving_dataset(n, m=8_000, seed=4)
+    r = np.random.default_rng(k)
+    C = (X[r.choice(len(X), k, replace=False)] + 0.05 * r.standard_normal((k, n))).astype(np.float32)
+    _check_objective(api, dev, X, C, f"narrow re-decisions n={n} k={k}")
+
+
 def test_objective_far_from_origin_needs_recheck(dev, api):
     # cancellation in ||c||^2 - 2 x.c is large here: the certified recheck decides
     r = np.random.default_rng(3)
@@ -388,6 +399,24 @@ def test_bigmeans_execution_modes_identical(dev, api, policy, seed):
         assert a["improvements"] == b["improvements"]
         assert np.array_equal(a["C_best"].cpu().numpy(), b["C_best"].cpu().numpy())
         assert np.array_equal(a["Y"].cpu().numpy(), b["Y"].cpu().numpy())
+
+
+def test_bigmeans_execution_modes_identical_cooperative_redecision(dev, api):
+    # k = 100 in 64-D: the round kernel re-decides a flagged point in one lane,
+    # the per-step kernels with the whole wave -- the same values and choices
+    X = datagen.serving_dataset(64, m=40_000, seed=5)
+    P = dict(k=100, workers=3, rounds_T=2, passes_p=2, s_min=3000, s_max=6000, seed=21,
+             size_policy=2)
+    say("bigmeans modes, cooperative re-decision", X.shape, P)
+    runs = [api.bigmeans_run(to_dev(X, dev), api.RunParams(batched=b, **P)) for b in (1, 2, 0)]
+    a = runs[0]
+    for b in runs[1:]:
+        assert a["f_full"] == b["f_full"] and a["s_opt"] == b["s_opt"]
+        assert a["best_worker"] == b["best_worker"] and a["lloyd_dists"] == b["lloyd_dists"]
+        assert np.array_equal(a["C_best"].cpu().numpy(), b["C_best"].cpu().numpy())
+        assert np.array_equal(a["Y"].cpu().numpy(), b["Y"].cpu().numpy())
+    o = obm.bigmeans_run(X, obm.Params(**P))
+    assert abs(a["f_full"] - o["f_full"]) <= 0.01 * o["f_full"]
 
 
 def test_bigmeans_shrink_policy_matches_oracle(dev, api):
