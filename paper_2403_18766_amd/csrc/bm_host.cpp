@@ -1129,6 +1129,12 @@ struct ServeGroup {
   int running = 0;
   hipStream_t stream = nullptr;   // the group's own stream (groups run concurrently)
   hipEvent_t store_ev = nullptr;  // recorded after the group's latest incumbent writes
+  // job states copied after a Lloyd iteration (pinned), read one iteration
+  // later so the host never waits for the iteration it has just launched
+  JobState* snap = nullptr;
+  hipEvent_t snap_ev = nullptr;
+  std::vector<int> snap_job;  // slot_job when the copy was taken
+  bool snap_pending = false;
 };
 
 // Device bytes one running job of sample size s uses (sample, indices, two
@@ -1148,6 +1154,8 @@ struct ServeState {
     for (ServeGroup& g : groups) {
       if (g.c) bm_destroy(g.c);  // synchronises the group's stream
       if (g.store_ev) (void)hipEventDestroy(g.store_ev);
+      if (g.snap_ev) (void)hipEventDestroy(g.snap_ev);
+      if (g.snap) (void)hipHostFree(g.snap);
       if (g.stream) (void)hipStreamDestroy(g.stream);
     }
     if (start_ev) (void)hipEventDestroy(start_ev);
@@ -1375,6 +1383,8 @@ int serve_impl(bm_ctx* c, const bm_dataset* ds, int nds, const bm_job* jobs, int
   for (ServeGroup& G : st.groups) {
     HIP_TRY(c, hipStreamCreateWithFlags(&G.stream, hipStreamNonBlocking));
     HIP_TRY(c, hipEventCreateWithFlags(&G.store_ev, hipEventDisableTiming));
+    HIP_TRY(c, hipEventCreateWithFlags(&G.snap_ev, hipEventDisableTiming));
+    HIP_TRY(c, hipHostMalloc((void**)&G.snap, (size_t)G.slots * sizeof(JobState), hipHostMallocDefault));
     HIP_TRY(c, hipStreamWaitEvent(G.stream, st.start_ev, 0));
     int rc = bm_create(c->device, G.stream, &G.c);
     if (rc != BM_OK) return c->fail(rc, "serving workspace: context creation failed");
@@ -1411,7 +1421,6 @@ int serve_impl(bm_ctx* c, const bm_dataset* ds, int nds, const bm_job* jobs, int
   auto elapsed = [&]() { return std::chrono::duration<double>(clock::now() - t0).count(); };
   int next = 0, done = 0;
   int64_t inflight = 0, steps = 0, peak_running = 0, peak_bytes = 0, running = 0;
-  std::vector<JobState> hs;
   while (done < njobs) {
     const double now = elapsed();
     while (next < njobs && (!sp.paced || jobs[order[next]].arrival <= now)) {
@@ -1463,8 +1472,11 @@ int serve_impl(bm_ctx* c, const bm_dataset* ds, int nds, const bm_job* jobs, int
       continue;
     }
     // one Lloyd iteration of every running job
-    for (ServeGroup& G : st.groups) {
+    std::vector<char> stepped(st.groups.size(), 0);
+    for (size_t gi = 0; gi < st.groups.size(); ++gi) {
+      ServeGroup& G = st.groups[gi];
       if (G.running == 0) continue;
+      stepped[gi] = 1;
       BatchView b;
       b.first = 0;
       b.njobs = G.slots;
@@ -1483,46 +1495,58 @@ int serve_impl(bm_ctx* c, const bm_dataset* ds, int nds, const bm_job* jobs, int
       BM_TRY(lloyd_launch(G.c, G.L, b, tm, G.s_max, -1));
     }
     ++steps;
-    // finished jobs leave; an accepted result becomes the worker's incumbent
+    // finished jobs leave; an accepted result becomes the worker's incumbent.
+    // The job states read here are those copied after the previous iteration
+    // (the device meanwhile runs this one); a job finished there is inactive
+    // in this iteration's launches, which skip it.
     for (size_t gi = 0; gi < st.groups.size(); ++gi) {
       ServeGroup& G = st.groups[gi];
-      if (G.running == 0) continue;
-      hs.resize(G.slots);
-      BM_TRY(readback(G.c, G.L.js, G.slots * sizeof(JobState), hs.data()));
-      bool wrote = false;
-      for (int q = 0; q < G.slots; ++q) {
-        const int j = G.slot_job[q];
-        if (j < 0 || hs[q].active) continue;
-        ServeWorker& W = workers[job_worker[j]];
-        bm_job_result& r = res[j];
-        r.f = hs[q].f;
-        r.iters = hs[q].iter;
-        r.accepted = hs[q].accepted;
-        r.ndeg = hs[q].ndeg;
-        if (hs[q].accepted) {
-          HIP_TRY(c, hipMemcpyAsync(st.store_c + W.off_c, P<float>(G.c->Cinc) + (int64_t)q * G.k * G.n,
-                                    (size_t)G.k * G.n * sizeof(float), hipMemcpyDeviceToDevice,
-                                    G.stream));
-          HIP_TRY(c, hipMemcpyAsync(st.store_deg + W.off_deg, P<uint8_t>(G.c->deg_inc) + (int64_t)q * G.k,
-                                    (size_t)G.k, hipMemcpyDeviceToDevice, G.stream));
-          W.store_group = (int)gi;
-          wrote = true;
-          W.fhat = hs[q].f;
-          W.ndeg = hs[q].ndeg;
+      if (G.snap_pending) {
+        HIP_TRY(c, hipEventSynchronize(G.snap_ev));
+        G.snap_pending = false;
+        bool wrote = false;
+        for (int q = 0; q < G.slots; ++q) {
+          const int j = G.snap_job[q];
+          if (j < 0 || G.slot_job[q] != j || G.snap[q].active) continue;
+          const JobState& hq = G.snap[q];
+          ServeWorker& W = workers[job_worker[j]];
+          bm_job_result& r = res[j];
+          r.f = hq.f;
+          r.iters = hq.iter;
+          r.accepted = hq.accepted;
+          r.ndeg = hq.ndeg;
+          if (hq.accepted) {
+            HIP_TRY(c, hipMemcpyAsync(st.store_c + W.off_c, P<float>(G.c->Cinc) + (int64_t)q * G.k * G.n,
+                                      (size_t)G.k * G.n * sizeof(float), hipMemcpyDeviceToDevice,
+                                      G.stream));
+            HIP_TRY(c, hipMemcpyAsync(st.store_deg + W.off_deg, P<uint8_t>(G.c->deg_inc) + (int64_t)q * G.k,
+                                      (size_t)G.k, hipMemcpyDeviceToDevice, G.stream));
+            W.store_group = (int)gi;
+            wrote = true;
+            W.fhat = hq.f;
+            W.ndeg = hq.ndeg;
+          }
+          r.f_incumbent = W.fhat;
+          r.finished = elapsed();
+          W.s_prev = jobs[j].s;
+          W.passes += 1;
+          W.busy = false;
+          G.slot_job[q] = -1;
+          G.sizes[q] = 0;
+          G.running -= 1;
+          running -= 1;
+          inflight -= serve_job_bytes(jobs[j].s, G.n, G.k);
+          ++done;
         }
-        r.f_incumbent = W.fhat;
-        r.finished = elapsed();
-        W.s_prev = jobs[j].s;
-        W.passes += 1;
-        W.busy = false;
-        G.slot_job[q] = -1;
-        G.sizes[q] = 0;
-        G.running -= 1;
-        running -= 1;
-        inflight -= serve_job_bytes(jobs[j].s, G.n, G.k);
-        ++done;
+        if (wrote) HIP_TRY(c, hipEventRecord(G.store_ev, G.stream));
       }
-      if (wrote) HIP_TRY(c, hipEventRecord(G.store_ev, G.stream));
+      if (G.running > 0 && stepped[gi]) {
+        G.snap_job = G.slot_job;
+        HIP_TRY(c, hipMemcpyAsync(G.snap, G.L.js, (size_t)G.slots * sizeof(JobState),
+                                  hipMemcpyDeviceToHost, G.stream));
+        HIP_TRY(c, hipEventRecord(G.snap_ev, G.stream));
+        G.snap_pending = true;
+      }
     }
   }
   for (ServeGroup& G : st.groups) HIP_TRY(c, hipStreamSynchronize(G.stream));
