@@ -149,47 +149,101 @@ def worker_pass(X, C, deg, fhat, s_prev, s, seed, worker, g, g_recalc, n_candida
             "accepted": accepted}
 
 
-def bigmeans_run(X, params, keep_trace=False):
+def worker_round(X, params, worker, t, state, bin_stats, l_stats):
+    """Round t of one worker (Algorithm 1, the body of the loop over workers):
+    its size draw, then p passes (the first one re-evaluates the incumbent if
+    the size changed).  state = (C, deg, fhat, s_prev).  Returns the new state,
+    the size, its bin and, per pass, (iters, accepted)."""
+    P = params
+    C, deg, fhat, s_prev = state
+    s_new, b = draw_size(P, worker, t, bin_stats, l_stats)
+    passes = []
+    for q in range(P.passes_p):
+        res = worker_pass(X, C, deg, fhat, s_prev, s_new, P.seed, worker, t * P.passes_p + q, t,
+                          P.n_candidates, P.max_iter, P.tol)
+        s_prev = s_new
+        C, deg, fhat = res["C"], res["deg"], res["fhat"]
+        passes.append((res["iters"], res["accepted"]))
+    return (C, deg, fhat, s_new), s_new, b, passes
+
+
+# Data of a process pool's workers (inherited through fork, never pickled).
+_POOL_X = None
+
+
+def _pool_init():
+    from threadpoolctl import threadpool_limits
+    threadpool_limits(limits=1)
+
+
+def _pool_round(args):
+    return worker_round(_POOL_X, *args)
+
+
+def bigmeans_run(X, params, keep_trace=False, processes=1, rounds_done=None):
     """Run Algorithm 1 on X (m x n).  Returns a dict with C_best, Y, s_opt,
-    f_full, the winning worker, the list L and per-round statistics."""
+    f_full, the winning worker, the list L and per-round statistics.
+
+    Workers depend on each other only through the list L (and the BINS and
+    SHRINK statistics of earlier rounds), so with processes > 1 each round's
+    workers run in a pool of that many processes (one BLAS thread each, the
+    paper's one worker per core); their results are merged in worker order,
+    which gives exactly the sequential run.  rounds_done(t, state) is called
+    after every round (optional)."""
+    global _POOL_X
     X = np.ascontiguousarray(X, dtype=np.float64)
     m, n = X.shape
     P = params
     W, k = P.workers, P.k
     if not (1 <= k <= P.s_min <= P.s_max <= m):
         raise ValueError("need 1 <= k <= s_min <= s_max <= m")
-    C = [np.zeros((k, n)) for _ in range(W)]
-    deg = [np.ones(k, dtype=bool) for _ in range(W)]
-    fhat = [math.inf] * W
-    s_cur = [None] * W
+    state = [(np.zeros((k, n)), np.ones(k, dtype=bool), math.inf, None) for _ in range(W)]
     L = []                                  # (round, worker, pass, s, bin)
     bin_stats = {"acc": [0] * N_BINS, "passes": [0] * N_BINS}
     lloyd_dists = 0
     lloyd_iters = 0
     rounds = []
-    for t in range(P.rounds_T):
-        round_acc = [0] * N_BINS
-        round_passes = [0] * N_BINS
-        l_stats = (sum(e[3] for e in L), len(L))   # L over earlier rounds
-        for w in range(W):
-            s_new, b = draw_size(P, w, t, bin_stats, l_stats)
-            for q in range(P.passes_p):
-                # the re-evaluation after a size change happens before the first pass
-                res = worker_pass(X, C[w], deg[w], fhat[w], s_cur[w], s_new, P.seed, w,
-                                  t * P.passes_p + q, t, P.n_candidates, P.max_iter, P.tol)
-                s_cur[w] = s_new
-                C[w], deg[w], fhat[w] = res["C"], res["deg"], res["fhat"]
-                lloyd_iters += res["iters"] + 1
-                lloyd_dists += (res["iters"] + 1) * s_new * k
-                round_passes[b] += 1
-                if res["accepted"]:
-                    L.append((t, w, q, s_new, b))
-                    round_acc[b] += 1
-        for i in range(N_BINS):
-            bin_stats["acc"][i] += round_acc[i]
-            bin_stats["passes"][i] += round_passes[i]
-        if keep_trace:
-            rounds.append({"C": [c.copy() for c in C], "fhat": list(fhat), "s": list(s_cur)})
+    pool = None
+    if processes > 1:
+        import multiprocessing as mp
+        _POOL_X = X
+        pool = mp.get_context("fork").Pool(processes, initializer=_pool_init)
+    try:
+        for t in range(P.rounds_T):
+            round_acc = [0] * N_BINS
+            round_passes = [0] * N_BINS
+            l_stats = (sum(e[3] for e in L), len(L))   # L over earlier rounds
+            stats_now = {"acc": list(bin_stats["acc"]), "passes": list(bin_stats["passes"])}
+            tasks = [(P, w, t, state[w], stats_now, l_stats) for w in range(W)]
+            if pool is None:
+                outs = [worker_round(X, *a) for a in tasks]
+            else:
+                outs = pool.map(_pool_round, tasks, chunksize=1)
+            for w, (st, s_new, b, passes) in enumerate(outs):
+                state[w] = st
+                for q, (iters, accepted) in enumerate(passes):
+                    lloyd_iters += iters + 1
+                    lloyd_dists += (iters + 1) * s_new * k
+                    round_passes[b] += 1
+                    if accepted:
+                        L.append((t, w, q, s_new, b))
+                        round_acc[b] += 1
+            for i in range(N_BINS):
+                bin_stats["acc"][i] += round_acc[i]
+                bin_stats["passes"][i] += round_passes[i]
+            if keep_trace:
+                rounds.append({"C": [s_[0].copy() for s_ in state], "fhat": [s_[2] for s_ in state],
+                               "s": [s_[3] for s_ in state]})
+            if rounds_done is not None:
+                rounds_done(t, state)
+    finally:
+        if pool is not None:
+            pool.close()
+            pool.join()
+            _POOL_X = None
+    C = [s_[0] for s_ in state]
+    deg = [s_[1] for s_ in state]
+    fhat = [s_[2] for s_ in state]
     if L:
         total = sum(e[3] for e in L)
         s_opt = (total + len(L) // 2) // len(L)

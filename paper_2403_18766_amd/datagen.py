@@ -143,6 +143,43 @@ def vmf_mixture_device(per_cluster, n, n_centres, device, seed=0, kappa=(50.0, 2
     return X.index_select(0, perm)
 
 
+def vmf_mixture_host(per_cluster, n, n_centres, seed=0, kappa=(50.0, 200.0), threads=None):
+    """The vmf_mixture_device recipe on the host, reproducible bit for bit on
+    any machine with this NumPy: mean directions, kappa and the row order from
+    default_rng(seed); cluster j's cosines (Wood's sampler) and tangent
+    directions from its own stream default_rng([seed, 1 + j]), so clusters
+    are drawn in parallel threads and the result does not depend on their
+    number.  Points are normalised in FP64 and stored FP32."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+    rng = np.random.default_rng(seed)
+    mus, kaps = [], []
+    for _ in range(n_centres):
+        mu = rng.standard_normal(n)
+        mus.append(mu / np.linalg.norm(mu))
+        kaps.append(rng.uniform(kappa[0], kappa[1]))
+    m = per_cluster * n_centres
+    X = np.empty((m, n), dtype=np.float32)
+
+    def one(j):
+        r = np.random.default_rng([seed, 1 + j])
+        mu = mus[j]
+        w = _vmf_cosines(r, kaps[j], n, per_cluster)[:, None]
+        v = r.standard_normal((per_cluster, n))
+        v -= (v @ mu)[:, None] * mu[None, :]
+        v /= np.linalg.norm(v, axis=1, keepdims=True)
+        x = w * mu[None, :] + np.sqrt(np.clip(1.0 - w * w, 0.0, None)) * v
+        x /= np.linalg.norm(x, axis=1, keepdims=True)
+        X[j * per_cluster: (j + 1) * per_cluster] = x
+
+    if threads is None:
+        threads = min(16, len(os.sched_getaffinity(0)))
+    with ThreadPoolExecutor(max(1, threads)) as ex:
+        list(ex.map(one, range(n_centres)))
+    perm = rng.permutation(m)
+    return np.ascontiguousarray(X[perm])
+
+
 # The five workloads (sizes of the configurations this code is measured on).
 WORKLOADS = {
     "blobs2d": dict(desc="20,000 points in 2-D from 5 isotropic Gaussians (centres U[-10,10]^2, "
@@ -171,6 +208,8 @@ def make(name, seed=0, m=None):
     if name == "noisy28":
         return noisy_mixture(mm, 28, 50, seed=seed)
     if name == "vmf768":
+        if m is None:   # the measured workload: reproducible host generator
+            return vmf_mixture_host(mm // 100, 768, 100, seed=seed)
         return vmf_mixture(max(1, mm // 100), 768, 100, seed=seed)
     raise KeyError(name)
 
@@ -182,3 +221,14 @@ def serving_dataset(n, m=4_000_000, seed=0):
 
 def sha256(X):
     return hashlib.sha256(np.ascontiguousarray(X).tobytes()).hexdigest()
+
+
+def sha256_chunked(X, chunk=1 << 26):
+    """sha256 of the concatenated sha256 digests of X's bytes in chunks of
+    `chunk` bytes (chunks hashed in parallel threads; for multi-GB inputs)."""
+    from concurrent.futures import ThreadPoolExecutor
+    buf = memoryview(np.ascontiguousarray(X)).cast("B")
+    parts = [buf[o: o + chunk] for o in range(0, len(buf), chunk)]
+    with ThreadPoolExecutor(8) as ex:
+        digests = list(ex.map(lambda b: hashlib.sha256(b).digest(), parts))
+    return hashlib.sha256(b"".join(digests)).hexdigest()

@@ -170,3 +170,16 @@ def test_recalc_on_size_change(blobs):
     for r in out["rounds"]:
         for w in range(2):
             assert math.isfinite(r["fhat"][w])
+
+
+def test_process_pool_equals_sequential(blobs):
+    # workers in a process pool, merged in worker order: exactly the sequential run
+    P = bigmeans.Params(k=4, workers=5, rounds_T=3, passes_p=2, s_min=300, s_max=1200,
+                        size_policy=bigmeans.SIZE_BINS, seed=8)
+    a = bigmeans.bigmeans_run(blobs, P, keep_trace=True)
+    b = bigmeans.bigmeans_run(blobs, P, keep_trace=True, processes=3)
+    assert a["L"] == b["L"] and a["f_full"] == b["f_full"] and a["s_opt"] == b["s_opt"]
+    assert np.array_equal(a["C_best"], b["C_best"])
+    assert a["lloyd_dists"] == b["lloyd_dists"]
+    for ra, rb in zip(a["rounds"], b["rounds"]):
+        assert ra["fhat"] == rb["fhat"] and ra["s"] == rb["s"]
