@@ -24,8 +24,12 @@
  *     pointers.  Calls with a host scalar output synchronise the context's
  *     stream before returning; calls without one only enqueue work.
  *   - All work is enqueued on the stream given to bm_create (0 = the legacy
- *     default stream).  The library owns only the workspace it allocates in
- *     bm_create/bm_reserve; no other call allocates device memory.
+ *     default stream).  The library owns only the workspace it allocates.
+ *     Device memory is allocated in bm_create/bm_reserve; a call whose sizes
+ *     exceed the reservation first grows it (bm_reserve's rule, before it
+ *     enqueues work); bm_serve allocates its serving state at its start and
+ *     frees it before returning (see there).  Nothing is allocated inside a
+ *     Lloyd iteration or a serving loop.
  *   - Return value: BM_OK (0) or a negative bm_status.  bm_strerror(ctx)
  *     describes the last error of that context.  No call aborts and no C++
  *     exception crosses this interface.
@@ -33,9 +37,11 @@
  *   - Sizes: 1 <= n <= 4096.  Points whose dimension rounded up to 4 is at
  *     most 64 are assigned with the point in registers and the centroids in
  *     LDS; wider points with FP32 matrix-core dot products.  k is limited by
- *     the LDS of one compute unit holding the fixed-point cluster sums
- *     (about 12 k * n + 8 k bytes <= 160 KiB for narrow points, k <= 310
- *     for wide ones); larger k returns BM_E_ARG.
+ *     the LDS of one compute unit holding the centroids and fixed-point
+ *     cluster sums: 12 k cp + 8 k bytes (cp = n rounded up to 4) plus the
+ *     assignment kernel's own LDS (at most about 1.4 KB) within 160 KiB for
+ *     narrow points, 516 k bytes plus 256 within 160 KiB (k <= 317) for wide
+ *     ones; larger k returns BM_E_ARG.
  *
  * Randomness (the paper fixes none).  Every random draw comes from the
  * Philox4x64-10 block function B(ctr, key) of Salmon et al. (SC'11) with
@@ -60,7 +66,7 @@ extern "C" {
 #define BM_API
 #endif
 
-#define BM_VERSION 1
+#define BM_VERSION 2
 
 typedef struct bm_ctx bm_ctx;
 
@@ -229,10 +235,14 @@ typedef struct bm_result {
 
 /* Per-round snapshot callback: after round `round` (0-based), C_all_dev holds
  * the W incumbents (W x k x n FP32, device, valid during the call),
- * fhat_host the W incumbent objectives, s_host the W sample sizes, and
+ * fhat_host the W incumbent objectives, s_host the W sample sizes, l_sum and
+ * l_count the sum and number of the sizes in the list L so far (so the final
+ * stage of Algorithm 1 after this round would draw its shared sample of size
+ * s_opt = (l_sum + l_count / 2) / l_count, or s_max if L is empty), and
  * t_seconds the device time elapsed since the start of the run. */
 typedef void (*bm_trace_cb)(void* user, int32_t round, const float* C_all_dev,
-                            const double* fhat_host, const int64_t* s_host, double t_seconds);
+                            const double* fhat_host, const int64_t* s_host, int64_t l_sum,
+                            int64_t l_count, double t_seconds);
 
 /* Algorithm 1 end to end on X (device, m x n FP32): per round and worker a
  * size draw and, on a size change, re-evaluation of the incumbent on a fresh
@@ -296,7 +306,8 @@ typedef struct bm_job_result {
 
 typedef struct bm_serve_params {
   uint64_t seed;
-  int64_t budget_bytes; /* device memory for job workspaces (samples, labels, sums) */
+  int64_t budget_bytes; /* device memory for job slots (samples, labels, sums): bounds both
+                           the reserved slots and the bytes of the jobs running together */
   int32_t max_slots;    /* running jobs per (dataset, k) at most */
   int32_t max_iter;     /* Lloyd update cap (Section 5: 300) */
   int32_t n_candidates; /* K-means++ candidates (Section 5: 3) */
@@ -316,8 +327,14 @@ typedef struct bm_serve_stats {
  *   datasets  host array of nds datasets (device rows).
  *   jobs      host array of njobs jobs.   results  host, njobs entries.
  *   stats     host (may be NULL).
- * Returns BM_E_ARG for invalid jobs or a budget too small for any slot.
- * Synchronises the stream. */
+ * Allocation: at its start, before any job runs, the call allocates the
+ * incumbent store (k x n floats and k flags per worker the jobs name) and,
+ * per (dataset, k, precision) group, a workspace of job slots, a stream, two
+ * events and a pinned copy of the group's job states; all of it is freed
+ * before the call returns.  The slots of all groups together hold at most
+ * budget_bytes (stats->slot_bytes); every group needs at least one slot.
+ * Returns BM_E_ARG for invalid jobs or a budget too small for one slot of
+ * every group.  Synchronises the stream. */
 BM_API int bm_serve(bm_ctx* ctx, const bm_dataset* datasets, int32_t nds, const bm_job* jobs,
                     int32_t njobs, const bm_serve_params* params, bm_job_result* results,
                     bm_serve_stats* stats);

@@ -180,7 +180,7 @@ def _pool_round(args):
     return worker_round(_POOL_X, *args)
 
 
-def bigmeans_run(X, params, keep_trace=False, processes=1, rounds_done=None):
+def bigmeans_run(X, params, keep_trace=False, processes=1, rounds_done=None, final_stage=True):
     """Run Algorithm 1 on X (m x n).  Returns a dict with C_best, Y, s_opt,
     f_full, the winning worker, the list L and per-round statistics.
 
@@ -189,7 +189,8 @@ def bigmeans_run(X, params, keep_trace=False, processes=1, rounds_done=None):
     workers run in a pool of that many processes (one BLAS thread each, the
     paper's one worker per core); their results are merged in worker order,
     which gives exactly the sequential run.  rounds_done(t, state) is called
-    after every round (optional)."""
+    after every round (optional).  With final_stage=False the run stops after
+    the rounds (no s_opt, final sample or full assignment)."""
     global _POOL_X
     X = np.ascontiguousarray(X, dtype=np.float64)
     m, n = X.shape
@@ -244,6 +245,9 @@ def bigmeans_run(X, params, keep_trace=False, processes=1, rounds_done=None):
     C = [s_[0] for s_ in state]
     deg = [s_[1] for s_ in state]
     fhat = [s_[2] for s_ in state]
+    if not final_stage:
+        return {"L": L, "fhat": fhat, "C_all": C, "deg_all": deg, "lloyd_dists": lloyd_dists,
+                "lloyd_iters": lloyd_iters, "rounds": rounds}
     if L:
         total = sum(e[3] for e in L)
         s_opt = (total + len(L) // 2) // len(L)

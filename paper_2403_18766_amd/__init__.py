@@ -15,7 +15,7 @@ from ._lib import (BM_FP32, BM_PURPOSE_FINAL, BM_PURPOSE_KMPP, BM_PURPOSE_RECALC
 
 def __getattr__(name):
     if name in ("sample", "seed", "lloyd", "objective", "bigmeans_run", "RunParams",
-                "draw_size", "philox4x64", "reserve", "paper_size_range", "BigmeansError"):
+                "draw_size", "philox4x64", "reserve", "BigmeansError"):
         from . import api
         return getattr(api, name)
     raise AttributeError(name)

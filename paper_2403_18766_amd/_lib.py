@@ -68,7 +68,8 @@ class ServeStats(ct.Structure):
 
 
 TRACE_CB = ct.CFUNCTYPE(None, ct.c_void_p, ct.c_int32, ct.c_void_p,
-                        ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64), ct.c_double)
+                        ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64), ct.c_int64, ct.c_int64,
+                        ct.c_double)
 
 # (name, restype, argtypes) for every function the header declares.
 SIGNATURES = [

@@ -7,8 +7,8 @@ contiguous, float32 (points, centroids), int32 (labels, indices) or uint8
 device; a context is created per (device, stream) and reused.
 """
 
+import atexit
 import ctypes as ct
-import math
 from dataclasses import dataclass
 
 import torch
@@ -25,6 +25,20 @@ class BigmeansError(RuntimeError):
 
 
 _contexts = {}
+
+
+def _release_contexts():
+    """At interpreter exit: finish each context's work and release its
+    workspace, pinned staging and events while the HIP runtime is still up."""
+    lib = _lib._lib
+    if lib is None:
+        return
+    for c in list(_contexts.values()):
+        lib.bm_destroy(c)
+    _contexts.clear()
+
+
+atexit.register(_release_contexts)
 
 
 def _ctx(device):
@@ -167,8 +181,10 @@ class RunParams:
 
 
 def bigmeans_run(X, params, labels=True, trace=None):
-    """bm_bigmeans_run (Algorithm 1).  `trace(round, C_all, fhat, sizes, t)`
-    is called after every round with a copy of the W incumbents (k x n each)."""
+    """bm_bigmeans_run (Algorithm 1).  `trace(round, C_all, fhat, sizes, t,
+    l_sum, l_count)` is called after every round with a copy of the W
+    incumbents (k x n each), the sum and count of the list L so far, and the
+    device time since the start of the run."""
     _dev(X, torch.float32, "X", 2)
     m, n = X.shape
     k = params.k
@@ -180,12 +196,13 @@ def bigmeans_run(X, params, labels=True, trace=None):
     W = params.workers
     cb = TRACE_CB(0)
     if trace is not None:
-        def _cb(user, rnd, c_all, fhat, sizes, tsec):
+        def _cb(user, rnd, c_all, fhat, sizes, l_sum, l_count, tsec):
             # a device-to-device copy of the incumbents on the library's stream
             snap = torch.empty((W, k, n), dtype=torch.float32, device=X.device)
             torch.cuda.synchronize(X.device)       # snap's allocation is complete
             _copy_device(snap, c_all, W * k * n * 4)
-            trace(rnd, snap, [fhat[i] for i in range(W)], [sizes[i] for i in range(W)], tsec)
+            trace(rnd, snap, [fhat[i] for i in range(W)], [sizes[i] for i in range(W)], tsec,
+                  l_sum, l_count)
         cb = TRACE_CB(_cb)
     rc = lib.bm_bigmeans_run(c, _ptr(X), ct.byref(cp), _ptr(C), _ptr(Y), ct.byref(res), cb, None)
     _check(lib, c, rc, allow_nonfinite=True)
@@ -261,11 +278,6 @@ def philox4x64(ctr, key):
     o4 = (ct.c_uint64 * 4)()
     lib.bm_philox4x64(c4, k2, o4)
     return tuple(int(v) for v in o4)
-
-
-def paper_size_range(s, m):
-    """Section 5: s_min = 0.5 s (rounded up), s_max = min(2 s, m)."""
-    return (int(s) + 1) // 2, min(2 * int(s), int(m))
 
 
 def serve(datasets, jobs, seed=0, budget_bytes=200 << 30, max_slots=64, max_iter=300, tol=1e-4,

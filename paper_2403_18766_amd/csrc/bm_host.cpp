@@ -1007,11 +1007,21 @@ int check_dim(bm_ctx* c, int n, int k) {
   if (n < 1) return c->fail(BM_E_ARG, "n must be >= 1");
   if (n > kMaxDim) return c->fail(BM_E_ARG, "n = %d exceeds the supported dimension %d", n, kMaxDim);
   if (k < 1) return c->fail(BM_E_ARG, "k must be >= 1");
-  // LDS of the fixed-point sums: k x cp (narrow) or k x 64 (wide) int64
+  // LDS of the Lloyd-step kernels: centroids, norms and fixed-point sums
+  // (k x cp floats and int64, narrow) or the sums' 64-dimension slice (wide),
+  // plus each kernel's static LDS
   const int cp = round_up4(n);
-  const size_t lds = cp > bm::kMaxRegDim ? bm::update_wide_lds(k)
-                                         : (size_t)k * cp * 12 + (size_t)k * 8 + 64;
-  if (lds > kMaxLds) return c->fail(BM_E_ARG, "k = %d is too large for n = %d", k, n);
+  size_t lds = 0, st = 0;
+  HIP_TRY(c, hipSetDevice(c->device));
+  if (cp > bm::kMaxRegDim) {
+    HIP_TRY(c, bm::update_wide_static_lds(&st));
+    lds = bm::update_wide_lds(k) + st;
+  } else {
+    HIP_TRY(c, bm::assign_static_lds(cp, k >= 64, &st));
+    lds = (((size_t)k * cp + k) * 4 + 15) / 16 * 16 + (size_t)k * cp * 8 + (size_t)k * 4 + st;
+  }
+  if (lds > kMaxLds)
+    return c->fail(BM_E_ARG, "k = %d is too large for n = %d (%zu bytes of LDS)", k, n, lds);
   return BM_OK;
 }
 
@@ -1361,6 +1371,26 @@ int serve_impl(bm_ctx* c, const bm_dataset* ds, int nds, const bm_job* jobs, int
     slots = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(slots, sp.max_slots), G.jobs));
     G.slots = (int)slots;
     total_slot_bytes += slots * per;
+  }
+  // every group holds at least one slot; if the rounding up to one slot put
+  // the total over the budget, take slots back from the groups holding the
+  // most bytes in slots beyond their first
+  while (total_slot_bytes > sp.budget_bytes) {
+    ServeGroup* take = nullptr;
+    int64_t most = 0;
+    for (ServeGroup& G : st.groups) {
+      const int64_t per = serve_job_bytes(G.s_max, G.n, G.k);
+      if (G.slots > 1 && (G.slots - 1) * per > most) {
+        most = (G.slots - 1) * per;
+        take = &G;
+      }
+    }
+    if (!take)
+      return c->fail(BM_E_ARG, "budget of %lld bytes is too small for one job slot of each of "
+                     "the %zu (dataset, k, precision) groups (%lld bytes)",
+                     (long long)sp.budget_bytes, st.groups.size(), (long long)total_slot_bytes);
+    take->slots -= 1;
+    total_slot_bytes -= serve_job_bytes(take->s_max, take->n, take->k);
   }
   // incumbent store: all centroids degenerate, f = +inf
   int64_t nc = 0, ndg = 0;
@@ -2062,7 +2092,7 @@ BM_API int bm_bigmeans_run(bm_ctx* c, const float* X, const bm_params* params, f
       HIP_TRY(c, hipEventSynchronize(c->ev1));
       float ms = 0.f;
       HIP_TRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
-      cb(user, t, P<float>(c->Cinc), fhat.data(), s_cur.data(), ms * 1e-3);
+      cb(user, t, P<float>(c->Cinc), fhat.data(), s_cur.data(), Lsum, Lcount, ms * 1e-3);
     }
   }
 

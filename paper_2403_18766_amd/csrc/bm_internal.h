@@ -118,6 +118,11 @@ hipError_t launch_update_wide(hipStream_t st, const float* S, int64_t S_stride, 
 hipError_t launch_finalize_wide(hipStream_t st, const FinalizeArgs& a, int32_t njobs);
 // LDS bytes of the wide update kernel for k clusters.
 size_t update_wide_lds(int32_t k);
+// Static LDS of the Lloyd-step assignment kernel of padded dimension cp (the
+// variant that re-decides flagged points with the whole wave when coop), and
+// of the wide update kernel; the dynamic LDS comes on top.
+hipError_t assign_static_lds(int32_t cp, bool coop, size_t* out);
+hipError_t update_wide_static_lds(size_t* out);
 hipError_t launch_job_init(hipStream_t st, JobState* js, const int64_t* sizes, int32_t njobs,
                            int32_t k, int32_t cp, unsigned long long* acc, int32_t* cnt,
                            const float* Cp, float* cn);

@@ -1752,6 +1752,21 @@ size_t round_lds_bytes(int32_t cp, int32_t k) {
     default: return hipErrorInvalidValue; \
   }
 
+template <int NP, bool COOP>
+hipError_t assign_static_lds_np(size_t* out) {
+  constexpr int PPL = NP <= 32 ? 2 : 1;
+  hipFuncAttributes fa;
+  hipError_t e = hipFuncGetAttributes(&fa, (const void*)k_assign_small<NP, PPL, true, COOP>);
+  if (e == hipSuccess) *out = fa.sharedSizeBytes;
+  return e;
+}
+
+hipError_t assign_static_lds(int32_t cp, bool coop, size_t* out) {
+#define BM_SL(NPV) (coop ? assign_static_lds_np<NPV, true>(out) : assign_static_lds_np<NPV, false>(out))
+  BM_ROUND_SWITCH(BM_SL)
+#undef BM_SL
+}
+
 hipError_t launch_xcd_probe(hipStream_t st, uint32_t* out, int32_t grid) {
   hipLaunchKernelGGL(k_xcd_probe, dim3(grid), dim3(64), 0, st, out);
   return hipGetLastError();

@@ -1000,6 +1000,13 @@ hipError_t launch_kpp_pot_staged(hipStream_t st, const KppArgs& a, int32_t njobs
   return hipGetLastError();
 }
 
+hipError_t update_wide_static_lds(size_t* out) {
+  hipFuncAttributes fa;
+  hipError_t e = hipFuncGetAttributes(&fa, (const void*)k_update_wide);
+  if (e == hipSuccess) *out = fa.sharedSizeBytes;
+  return e;
+}
+
 size_t update_wide_lds(int32_t k) {
   return (size_t)k * kUpdDims * sizeof(unsigned long long) + (size_t)k * sizeof(int);
 }

@@ -43,6 +43,52 @@ def test_header_compiles_as_c(tmp_path):
     assert r.returncode == 0, r.stderr
 
 
+def test_c_program_links_and_calls_the_library(lib, tmp_path):
+    # a C program built against the header and linked with libbigmeans.so
+    # calls the host-only entry points; its output must match the oracle
+    from paper_2403_18766_amd import _lib
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "prog.c"
+    src.write_text(r"""
+#include <inttypes.h>
+#include <stdio.h>
+#include "bigmeans.h"
+int main(void) {
+  uint64_t ctr[4] = {3, 1, 4, 1}, key[2] = {5, 9}, out[4];
+  bm_philox4x64(ctr, key, out);
+  printf("%d\n", bm_version());
+  printf("%" PRIu64 " %" PRIu64 " %" PRIu64 " %" PRIu64 "\n", out[0], out[1], out[2], out[3]);
+  bm_params p = {0};
+  p.m = 1000000; p.s_min = 4096; p.s_max = 65536; p.n = 28; p.k = 25; p.workers = 32;
+  p.size_policy = BM_SIZE_LOGUNIFORM; p.seed = 0;
+  for (int t = 0; t < 3; ++t) {
+    int64_t s; int32_t b;
+    if (bm_draw_size(&p, 7, t, NULL, NULL, 0, 0, &s, &b) != BM_OK) return 2;
+    printf("%" PRId64 "\n", s);
+  }
+  p.s_min = 0;
+  int64_t s; int32_t b;
+  return bm_draw_size(&p, 7, 0, NULL, NULL, 0, 0, &s, &b) == BM_E_ARG ? 0 : 3;
+}
+""")
+    exe = tmp_path / "prog"
+    libdir = os.path.dirname(_lib.LIB_PATH)
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-I", os.path.dirname(HEADER),
+                        str(src), "-o", str(exe), "-L", libdir, "-lbigmeans",
+                        "-Wl,-rpath," + libdir], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, (r.returncode, r.stderr)
+    lines = r.stdout.split()
+    assert int(lines[0]) == 2
+    assert tuple(int(v) for v in lines[1:5]) == orng.philox_block_scalar((3, 1, 4, 1), (5, 9))
+    P = obm.Params(k=25, workers=32, rounds_T=3, s_min=4096, s_max=65536,
+                   size_policy=obm.SIZE_LOGUNIFORM, seed=0)
+    assert [int(v) for v in lines[5:8]] == [obm.draw_size(P, 7, t, None)[0] for t in range(3)]
+
+
 def test_every_declared_symbol_is_exported(lib):
     from paper_2403_18766_amd import _lib
     declared = _declared_functions()
@@ -51,7 +97,7 @@ def test_every_declared_symbol_is_exported(lib):
     assert set(declared) == bound
     for name in declared:
         assert hasattr(lib, name), name
-    assert lib.bm_version() == 1
+    assert lib.bm_version() == 2
 
 
 def test_struct_layout_matches_header(lib):

@@ -446,10 +446,11 @@ def test_bigmeans_trace_and_nan_rows(dev, api):
     P = api.RunParams(k=3, workers=2, rounds_T=2, passes_p=2, s_min=500, s_max=500,
                       size_policy=1, seed=5)
     seen = []
-    g = api.bigmeans_run(to_dev(X, dev), P, trace=lambda r, C, fh, s, t: seen.append((r, list(fh))))
+    g = api.bigmeans_run(to_dev(X, dev), P, trace=lambda r, C, fh, s, t, *L: seen.append((r, list(fh), L)))
     assert g["improvements"] == 0
-    assert [r for r, _ in seen] == [0, 1]
-    assert all(math.isinf(f) for _, fh in seen for f in fh)
+    assert [r for r, _, _ in seen] == [0, 1]
+    assert all(math.isinf(f) for _, fh, _ in seen for f in fh)
+    assert all(L == (0, 0) for _, _, L in seen)     # nothing accepted: L stays empty
 
 
 @pytest.mark.parametrize("n", [36, 64])

@@ -63,9 +63,13 @@ def test_serve_alone_equals_mix(dev, api):
     alone, st_alone = api.serve(Xd, jobs, seed=3, max_slots=1)
     assert st_mix["peak_running"] > 1 and st_alone["peak_running"] <= len(Xs) * 2
     assert _fields(mix) == _fields(alone)
-    # a smaller budget admits fewer jobs at once and still gives the same results
-    small, st_small = api.serve(Xd, jobs, seed=3, max_slots=16, budget_bytes=st_mix["peak_bytes"] // 2)
-    assert st_small["peak_bytes"] <= st_mix["peak_bytes"] // 2
+    # a smaller budget (but room for one slot of every group) admits fewer
+    # jobs at once and still gives the same results
+    budget = max(st_mix["peak_bytes"] // 2, st_alone["slot_bytes"])
+    small, st_small = api.serve(Xd, jobs, seed=3, max_slots=16, budget_bytes=budget)
+    assert st_small["peak_bytes"] <= budget and st_small["slot_bytes"] <= budget
+    assert st_small["peak_running"] <= st_mix["peak_running"]
+    assert st_mix["slot_bytes"] <= 200 << 30
     assert _fields(small) == _fields(mix)
 
 
@@ -123,3 +127,24 @@ def test_serve_rejects_invalid(dev, api):
         api.serve([X], [dict(s=50, dataset=1, k=2, worker=0)])       # no such data set
     with pytest.raises(BigmeansError):
         api.serve([X], [dict(s=50, dataset=0, k=2, worker=0)], budget_bytes=1)
+
+
+def test_serve_budget_bounds_reserved_slots(dev, api):
+    # many (dataset, k) groups and a budget just above one slot each: the
+    # reserved slots stay within the budget, results unchanged; below one
+    # slot per group the call is refused
+    from paper_2403_18766_amd.api import BigmeansError
+    Xs = _datasets()
+    Xd = [to_dev(X, dev) for X in Xs]
+    jobs = _jobs(len(Xs), 36, 4, ks=(3, 5, 8), workers=2)
+    ref, st_ref = api.serve(Xd, jobs, seed=2, max_slots=16)
+    one_each = st_ref["slot_bytes"] // max(1, st_ref["peak_running"])
+    # the bytes of one slot of every group, from a run with one slot each
+    _, st_one = api.serve(Xd, jobs, seed=2, max_slots=1)
+    budget = st_one["slot_bytes"] + st_one["slot_bytes"] // 4
+    res, st = api.serve(Xd, jobs, seed=2, max_slots=16, budget_bytes=budget)
+    say("serve budget", budget, "slots", st["slot_bytes"], "one each", st_one["slot_bytes"], one_each)
+    assert st["slot_bytes"] <= budget and st["peak_bytes"] <= budget
+    assert _fields(res) == _fields(ref)
+    with pytest.raises(BigmeansError):
+        api.serve(Xd, jobs, seed=2, max_slots=16, budget_bytes=st_one["slot_bytes"] - 1)
