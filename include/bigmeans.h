@@ -195,6 +195,23 @@ BM_API int bm_objective(bm_ctx* ctx, const float* X, int64_t m, int32_t n, const
                         int32_t k, int32_t prec, double* f_out, int32_t* labels_out,
                         int64_t* near_ties_out);
 
+/* bm_objective for callers that cannot allocate memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  Same
+ * arguments, results and errors as bm_objective (same kernels, same bits),
+ * but the call allocates nothing: its workspace (tile map, padded centroids
+ * and norms, one FP64 partial and near-tie count per 256 points, the results)
+ * is a static device array of 16 MiB per GPU that the library holds until
+ * the process ends, and its scalar results are copied straight into f_out
+ * and near_ties_out.  Sizes whose workspace exceeds the array (about
+ * 12 bytes per 256 points + 4 k (cp + 1) bytes, cp = n rounded up to 4, e.g.
+ * m up to about 300 million points at small k) return BM_E_ARG.  Every call
+ * on one GPU shares that array, which keeps the last call's contents: calls
+ * that overlap on one GPU (other streams or host threads) race and must be
+ * serialised by the caller.  Synchronises the stream. */
+BM_API int bm_objective_noalloc(bm_ctx* ctx, const float* X, int64_t m, int32_t n,
+                                const float* C, int32_t k, int32_t prec, double* f_out,
+                                int32_t* labels_out, int64_t* near_ties_out);
+
 /* Parameters of Algorithm 1. */
 typedef struct bm_params {
   int64_t m;           /* rows of X */

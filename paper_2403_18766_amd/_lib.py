@@ -91,6 +91,10 @@ SIGNATURES = [
     ("bm_objective", ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_void_p,
                                 ct.c_int32, ct.c_int32, ct.POINTER(ct.c_double), ct.c_void_p,
                                 ct.POINTER(ct.c_int64)]),
+    ("bm_objective_noalloc", ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int32,
+                                        ct.c_void_p, ct.c_int32, ct.c_int32,
+                                        ct.POINTER(ct.c_double), ct.c_void_p,
+                                        ct.POINTER(ct.c_int64)]),
     ("bm_bigmeans_run", ct.c_int, [ct.c_void_p, ct.c_void_p, ct.POINTER(Params), ct.c_void_p,
                                    ct.c_void_p, ct.POINTER(Result), TRACE_CB, ct.c_void_p]),
     ("bm_draw_size", ct.c_int, [ct.POINTER(Params), ct.c_uint32, ct.c_int32,

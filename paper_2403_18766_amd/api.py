@@ -154,6 +154,29 @@ def objective(X, C, labels=True, near_ties=True, prec=BM_FP32):
     return f.value, lab, (near.value if near_ties else None)
 
 
+def objective_noalloc(X, C, labels_out=None, near_ties=True, prec=BM_FP32):
+    """bm_objective_noalloc: bm_objective with the library's static workspace
+    (no allocation in the call).  labels_out: an int32 device tensor of m
+    entries, or None.  Returns (f, near-tie count or None)."""
+    _dev(X, torch.float32, "X", 2)
+    _dev(C, torch.float32, "C", 2)
+    m, n = X.shape
+    k = C.shape[0]
+    if C.shape[1] != n:
+        raise ValueError("C and X differ in dimension")
+    if labels_out is not None:
+        _dev(labels_out, torch.int32, "labels_out", 1)
+        if labels_out.shape[0] != m:
+            raise ValueError("labels_out must have one entry per row of X")
+    f = ct.c_double()
+    near = ct.c_int64()
+    lib, c = _ctx(X.device)
+    rc = lib.bm_objective_noalloc(c, _ptr(X), m, n, _ptr(C), k, int(prec), ct.byref(f),
+                                  _ptr(labels_out), ct.byref(near) if near_ties else None)
+    _check(lib, c, rc, allow_nonfinite=True)
+    return f.value, (near.value if near_ties else None)
+
+
 @dataclass
 class RunParams:
     """Parameters of Algorithm 1 (defaults are those of Section 5)."""

@@ -7,7 +7,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbigmeans.so")
-SOURCES = ["bm_kernels.hip", "bm_wide.hip", "bm_host.cpp"]
+SOURCES = ["bm_kernels.hip", "bm_wide.hip", "bm_noalloc.hip", "bm_host.cpp"]
 
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-fvisibility=hidden",

@@ -79,6 +79,8 @@ struct bm_ctx {
   void* rb = nullptr;
   size_t rb_bytes = 0;
 
+  void* scratch = nullptr;  // this device's static workspace (bm_objective_noalloc)
+
   hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
   hipEvent_t tev0 = nullptr, tev1 = nullptr;  // tile tuning
 
@@ -1616,6 +1618,11 @@ BM_API int bm_create(int device, void* hip_stream, bm_ctx** out) {
   }
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
+  // address of the no-allocation workspace on this device (device current)
+  if (bm::noalloc_scratch(device, &c->scratch) != hipSuccess) {
+    delete c;
+    return BM_E_STATE;
+  }
   bool ok = true;
   for (int i = 0; i < kNumStage && ok; ++i) {
     ok = hipHostMalloc(&c->stage[i], kStageBytes, hipHostMallocDefault) == hipSuccess &&
@@ -1786,6 +1793,92 @@ BM_API int bm_objective(bm_ctx* c, const float* X, int64_t m, int32_t n, const f
     BM_TRY(readback(c, c->nearjob.p, sizeof(long long), &nn));
     *near_ties_out = nn;
   }
+  if (!std::isfinite(f)) return c->fail(BM_E_NONFINITE, "objective is not finite");
+  return BM_OK;
+}
+
+BM_API int bm_objective_noalloc(bm_ctx* c, const float* X, int64_t m, int32_t n, const float* C,
+                                int32_t k, int32_t prec, double* f_out, int32_t* labels_out,
+                                int64_t* near_ties_out) {
+  if (!c) return BM_E_ARG;
+  if (!X || !C || !f_out) return c->fail(BM_E_ARG, "X, C and f_out are required");
+  if (k < 1 || m < 1) return c->fail(BM_E_ARG, "need k >= 1, m >= 1");
+  BM_TRY(check_prec(c, prec));
+  BM_TRY(check_dim(c, n, k));
+  if (!c->scratch) return c->fail(BM_E_STATE, "no static workspace on device %d", c->device);
+  // layout of the static workspace (256-byte aligned pieces)
+  const int cp = round_up4(n);
+  const int64_t chunks = (m + bm::kWG - 1) / bm::kWG;
+  const int64_t step = 2 * bm::kWG;  // the tile size rule of the allocating path
+  const int64_t tile_steps = std::max<int64_t>(1, (m + step * 1024 - 1) / (step * 1024));
+  const int64_t tile_pts = tile_steps * step;
+  const int64_t ntiles = (m + tile_pts - 1) / tile_pts;
+  auto al = [](int64_t v) { return (v + 255) & ~(int64_t)255; };
+  const int64_t o_tf = 0;
+  const int64_t o_near = o_tf + al(chunks * 8);
+  const int64_t o_tjob = o_near + al(chunks * 4);
+  const int64_t o_tidx = o_tjob + al(ntiles * 4);
+  const int64_t o_cp = o_tidx + al(ntiles * 4);
+  const int64_t o_cn = o_cp + al((int64_t)k * cp * 4);
+  const int64_t o_size = o_cn + al((int64_t)k * 4);
+  const int64_t o_f = o_size + 256;
+  const int64_t o_nn = o_f + 256;
+  const int64_t total = o_nn + 256;
+  if (total > (int64_t)bm::kNoallocScratchBytes)
+    return c->fail(BM_E_ARG,
+                   "m = %lld, n = %d, k = %d needs %lld bytes of workspace; the static workspace "
+                   "holds %zu",
+                   (long long)m, n, k, (long long)total, bm::kNoallocScratchBytes);
+  HIP_TRY(c, hipSetDevice(c->device));
+  unsigned char* base = static_cast<unsigned char*>(c->scratch);
+  double* tf = reinterpret_cast<double*>(base + o_tf);
+  int32_t* tnear = near_ties_out ? reinterpret_cast<int32_t*>(base + o_near) : nullptr;
+  int32_t* tjob = reinterpret_cast<int32_t*>(base + o_tjob);
+  int32_t* tidx = reinterpret_cast<int32_t*>(base + o_tidx);
+  float* Cp = reinterpret_cast<float*>(base + o_cp);
+  float* cn = reinterpret_cast<float*>(base + o_cn);
+  int64_t* sizes = reinterpret_cast<int64_t*>(base + o_size);
+  double* f_dev = reinterpret_cast<double*>(base + o_f);
+  long long* near_dev = reinterpret_cast<long long*>(base + o_nn);
+  hipStream_t st = c->stream;
+  HIP_TRY(c, bm::launch_noalloc_tiles(st, tjob, tidx, (int32_t)ntiles, sizes, m));
+  HIP_TRY(c, bm::launch_pad_centroids(st, C, 0, n, cp, k, 1, Cp, 0, cn, 0));
+  bm::AssignArgs a{};
+  a.S = X;
+  a.S_stride = 0;
+  a.ld = n;
+  a.n = n;
+  a.cp = cp;
+  a.k = k;
+  a.tile_pts = (int32_t)tile_pts;
+  a.max_chunks = (int32_t)chunks;
+  a.vec = (n == cp && aligned16(X)) ? 1 : 0;
+  a.s = sizes;
+  a.tile_job = tjob;
+  a.tile_idx = tidx;
+  a.Cp = Cp;
+  a.C_stride = (int64_t)k * cp;
+  a.cn = cn;
+  a.cn_stride = k;
+  a.labels = labels_out;
+  a.lab_stride = 0;
+  a.tf = tf;
+  a.tnear = tnear;
+  if (cp > bm::kMaxRegDim && prec == BM_BF16)
+    HIP_TRY(c, bm::launch_assign_wide_bf16(st, a, (int32_t)ntiles, false));
+  else if (cp > bm::kMaxRegDim)
+    HIP_TRY(c, bm::launch_assign_wide(st, a, (int32_t)ntiles, false));
+  else
+    HIP_TRY(c, bm::launch_assign(st, a, (int32_t)ntiles, false));
+  HIP_TRY(c, bm::launch_reduce_f(st, tf, tnear, sizes, (int32_t)chunks, 1, f_dev,
+                                 near_ties_out ? near_dev : nullptr));
+  double f = 0.0;
+  long long nn = 0;
+  HIP_TRY(c, hipMemcpyAsync(&f, f_dev, sizeof f, hipMemcpyDeviceToHost, st));
+  if (near_ties_out) HIP_TRY(c, hipMemcpyAsync(&nn, near_dev, sizeof nn, hipMemcpyDeviceToHost, st));
+  HIP_TRY(c, hipStreamSynchronize(st));
+  *f_out = f;
+  if (near_ties_out) *near_ties_out = nn;
   if (!std::isfinite(f)) return c->fail(BM_E_NONFINITE, "objective is not finite");
   return BM_OK;
 }

@@ -89,6 +89,15 @@ struct FinalizeArgs {
   double* fhat;                   // [job]
 };
 
+// ---- static workspace of the no-allocation objective (bm_noalloc.hip) ----
+constexpr size_t kNoallocScratchBytes = (size_t)16 << 20;
+// Device address of the static workspace on `device`, which must be the
+// current device; looked up on the first call per device, then cached.
+hipError_t noalloc_scratch(int device, void** out);
+// Tile map (tile t -> job 0, tile index t) and size m of a one-job launch.
+hipError_t launch_noalloc_tiles(hipStream_t st, int32_t* tile_job, int32_t* tile_idx,
+                                int32_t ntiles, int64_t* sizes, int64_t m);
+
 // ---- launchers (bm_kernels.hip) ----
 hipError_t launch_sample(hipStream_t st, const float* X, int64_t m, int32_t n, int32_t njobs,
                          int64_t max_s, const int64_t* s, const uint64_t* rkeys, int32_t* idx,
