@@ -194,6 +194,44 @@ def test_lloyd_one_update_teacher_forced(dev, api, name, m, k, seed):
     assert np.array_equal(res["deg"].cpu().numpy().astype(bool), cnt1 == 0)
 
 
+def test_lloyd_update_dimension_set_by_an_outlier(dev, api):
+    # The centroid sums are exact fixed-point integers with 2^-shift_d
+    # resolution, shift_d = 62 - e_d - ceil(log2 s) where |x_d| < 2^e_d over the
+    # data: a mean whose magnitude is far below the dimension's largest value
+    # (here one point at 1e7 among values near 1e-2) is only good to 2^-shift_d
+    # absolute, many FP32 ulps.  Check that documented bound everywhere, and
+    # 1 ulp where |mean| >= 2^-21 max|x_d|.
+    r = np.random.default_rng(11)
+    m, n, k = 4096, 4, 6
+    centres = r.uniform(-1e-2, 1e-2, size=(k - 1, n))
+    S = centres[r.integers(k - 1, size=m)] + 1e-3 * r.standard_normal((m, n))
+    S[17, 2] = 1.0e7
+    S = S.astype(np.float32)
+    C0 = np.ascontiguousarray(S[[0, 1, 2, 3, 4, 17]])
+    res = api.lloyd(to_dev(S, dev), to_dev(C0, dev), max_iter=1, tol=0.0)
+    assert res["iters"] == 1
+    C1 = res["C"].cpu().numpy().astype(np.float64)
+    lab0, _, _, near0 = okm.assign(S, C0, return_second=True)
+    want, _ = okm.cluster_means(S, lab0, k, C0)
+    touched = np.zeros(k, bool)
+    touched[np.unique(lab0[near0])] = True
+    L = int(math.ceil(math.log2(m)))
+    e = np.array([math.frexp(float(v))[1] for v in np.abs(S.astype(np.float64)).max(axis=0)])
+    shift = 62 - e - L
+    w32 = want.astype(np.float32)
+    half_ulp = 0.5 * np.abs(np.spacing(w32)).astype(np.float64)
+    bound = np.ldexp(1.0, -shift)[None, :] + half_ulp
+    err = np.abs(C1 - want)
+    assert np.all(err[~touched] <= bound[~touched]), (err / bound)[~touched].max()
+    big = np.abs(want) >= np.ldexp(np.abs(S.astype(np.float64)).max(axis=0), -21)[None, :]
+    u = ulp_diff_f32(C1.astype(np.float32), w32)
+    assert np.all(u[~touched][big[~touched]] <= 1)
+    # the outlier's own cluster is exact, and dimension 2 is the limited one
+    assert C1[5, 2] == 1.0e7
+    assert not big[:5, 2].any()
+    say("outlier dimension: max ulp error where the bound is relaxed", int(u[~touched][~big[~touched]].max()))
+
+
 @pytest.mark.parametrize("name,m,k,seed", [("blobs2d", 2_000, 5, 3), ("aniso28", 22_161, 25, 4),
                                            ("noisy28", 40_000, 50, 5)])
 def test_lloyd_full_run_matches_oracle(dev, api, name, m, k, seed):
