@@ -804,10 +804,10 @@ int round_persistent(bm_ctx* c, const float* X, const bm_params& p, int t,
   const int W = p.workers, k = p.k, n = p.n, cp = round_up4(n);
   const size_t lds = bm::round_lds_bytes(cp, k);
   int cap = 0;
-  HIP_TRY(c, bm::round_capacity(cp, lds, &cap));
+  HIP_TRY(c, bm::round_capacity(cp, k, lds, &cap));
   if (cap < W) return kRoundNoFit;
   BM_TRY(xcd_layout(c, cap));
-  const int ppl = cp <= 32 ? 2 : 1;
+  const int ppl = (cp <= 32 && k < bm::kMfmaMinK) ? 2 : 1;  // points per lane of k_round
   constexpr double kF = 20.0, kL = 16.0;  // relative costs (microseconds, measured)
   std::vector<int64_t> units(W);
   std::vector<double> work(W);
@@ -980,7 +980,7 @@ int round_persistent(bm_ctx* c, const float* X, const bm_params& p, int t,
   BM_TRY(upload(c, c->rargs.p, &r, sizeof r));
 
   HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
-  HIP_TRY(c, bm::launch_round(c->stream, P<bm::RoundArgs>(c->rargs), cp, cap, lds));
+  HIP_TRY(c, bm::launch_round(c->stream, P<bm::RoundArgs>(c->rargs), cp, k, cap, lds));
   HIP_TRY(c, hipEventRecord(c->ev2, c->stream));
   std::vector<unsigned char> h(rres_bytes);
   BM_TRY(readback(c, rr, rres_bytes, h.data()));
@@ -1019,7 +1019,7 @@ int check_dim(bm_ctx* c, int n, int k) {
     HIP_TRY(c, bm::update_wide_static_lds(&st));
     lds = bm::update_wide_lds(k) + st;
   } else {
-    HIP_TRY(c, bm::assign_static_lds(cp, k >= 64, &st));
+    HIP_TRY(c, bm::assign_static_lds(cp, &st));
     lds = (((size_t)k * cp + k) * 4 + 15) / 16 * 16 + (size_t)k * cp * 8 + (size_t)k * 4 + st;
   }
   if (lds > kMaxLds)

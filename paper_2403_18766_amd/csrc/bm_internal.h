@@ -12,6 +12,10 @@ namespace bm {
 constexpr int kWG = 256;         // threads per workgroup (4 wave64s)
 constexpr int kMaxRegDim = 64;   // largest padded dimension kept in registers
 constexpr int kDTile = 256;      // points per K-means++ tile
+// From this many centres on, the persistent round kernel ranks centres on the
+// FP32 matrix cores with one point per lane; below, with FP32 FMAs and two
+// points per lane up to 32 dimensions.
+constexpr int kMfmaMinK = 16;
 
 // Lloyd state of one job (one sample with its centroids).
 struct JobState {
@@ -127,10 +131,9 @@ hipError_t launch_update_wide(hipStream_t st, const float* S, int64_t S_stride, 
 hipError_t launch_finalize_wide(hipStream_t st, const FinalizeArgs& a, int32_t njobs);
 // LDS bytes of the wide update kernel for k clusters.
 size_t update_wide_lds(int32_t k);
-// Static LDS of the Lloyd-step assignment kernel of padded dimension cp (the
-// variant that re-decides flagged points with the whole wave when coop), and
-// of the wide update kernel; the dynamic LDS comes on top.
-hipError_t assign_static_lds(int32_t cp, bool coop, size_t* out);
+// Static LDS of the Lloyd-step assignment kernel of padded dimension cp and of
+// the wide update kernel; the dynamic LDS comes on top.
+hipError_t assign_static_lds(int32_t cp, size_t* out);
 hipError_t update_wide_static_lds(size_t* out);
 hipError_t launch_job_init(hipStream_t st, JobState* js, const int64_t* sizes, int32_t njobs,
                            int32_t k, int32_t cp, unsigned long long* acc, int32_t* cnt,
@@ -217,11 +220,11 @@ struct RoundArgs {
 // XCD id of every workgroup of a grid-sized launch: out[grid].
 hipError_t launch_xcd_probe(hipStream_t st, uint32_t* out, int32_t grid);
 // Largest grid of k_round<cp> that is co-resident on the device.
-hipError_t round_capacity(int32_t cp, size_t lds, int* blocks);
+hipError_t round_capacity(int32_t cp, int32_t k, size_t lds, int* blocks);
 size_t round_lds_bytes(int32_t cp, int32_t k);
 // r_dev: the RoundArgs in device memory (read by every workgroup).
-hipError_t launch_round(hipStream_t st, const RoundArgs* r_dev, int32_t cp, int32_t grid,
-                        size_t lds);
+hipError_t launch_round(hipStream_t st, const RoundArgs* r_dev, int32_t cp, int32_t k,
+                        int32_t grid, size_t lds);
 
 hipError_t launch_kpp_setup(hipStream_t st, const KppArgs& a, int32_t njobs);
 hipError_t launch_kpp_init(hipStream_t st, const KppArgs& a, int32_t njobs, int64_t max_s);

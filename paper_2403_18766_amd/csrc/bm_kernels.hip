@@ -269,6 +269,87 @@ __global__ __launch_bounds__(kWG) void k_unpad(const float* __restrict__ Cp, int
 }
 
 // ---------------------------------------------------------------------------
+// Ranking on the FP32 matrix cores (from kMfmaMinK centres on).  The wave's
+// 64 points (lane l: point l, its row in registers) form two 32-point blocks;
+// v_mfma_f32_32x32x2f32 takes, per step of two dimensions, the centres of a
+// 32-centre tile as operand A (lane (h, c): centre c of the tile, dimension
+// 2q + h) and a block's points as operand B (lane (h, c): point c of the block,
+// dimension 2q + h).  One v_permlane32_swap of the rows' dimensions 2q and
+// 2q + 1 gives the B operands of both blocks.  Lane (h, c) then holds, for
+// point c of each block, the dot products with the tile's centres
+// 8 (v / 4) + 4 h + v % 4 (v < 16), keeps a running best and second best, and
+// the two halves of every point's centre set merge with one lane exchange
+// (lowest index on equal values).  The products are summed in an order the
+// hardware chooses, so the certification bound takes gamma for NP + 1 terms.
+// ---------------------------------------------------------------------------
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ inline void top2_merge_narrow(float& e1, int& j1, float& e2, float oe1, int oj1,
+                                         float oe2) {
+  if (oe1 < e1 || (oe1 == e1 && oj1 < j1)) {
+    e2 = fminf(e1, oe2);
+    e1 = oe1;
+    j1 = oj1;
+  } else {
+    e2 = fminf(e2, oe1);
+  }
+}
+
+// Best and second-best e_j = ||c_j||^2 - 2 x.c_j over the k centres in LDS
+// (sC rows of NP floats, norms sCn) for this lane's point x, best index j1.
+template <int NP>
+__device__ inline void mfma_rank(const float (&x)[NP], const float* sC, const float* sCn, int k,
+                                 float& e1o, float& e2o, int& j1o) {
+  const int lane = threadIdx.x & 63;
+  const int h = lane >> 5, col = lane & 31;
+  float e1[2] = {__builtin_inff(), __builtin_inff()};
+  float e2[2] = {__builtin_inff(), __builtin_inff()};
+  int j1[2] = {0, 0};
+  for (int t0 = 0; t0 < k; t0 += 32) {  // one tile of 32 centres per pass
+    f32x16 acc[2];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[b][v] = 0.f;
+    // rows past the last centre repeat it (their products are never ranked)
+    const float* a0 = sC + min(t0 + col, k - 1) * NP + h;
+#pragma unroll
+    for (int q = 0; q < NP / 2; ++q) {
+      const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(x[2 * q]),
+                                                       __float_as_uint(x[2 * q + 1]), false, false);
+      const float av = a0[2 * q];
+      acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, __uint_as_float(sw[0]), acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, __uint_as_float(sw[1]), acc[1], 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int c = t0 + 8 * (v >> 2) + 4 * h + (v & 3);
+      if (c < k) {
+        const float cnc = sCn[c];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const float e = fmaf(-2.f, acc[b][v], cnc);
+          e2[b] = __builtin_amdgcn_fmed3f(e1[b], e, e2[b]);
+          j1[b] = e < e1[b] ? c : j1[b];
+          e1[b] = fminf(e1[b], e);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const float oe1 = __shfl_xor(e1[b], 32, 64);
+    const int oj1 = __shfl_xor(j1[b], 32, 64);
+    const float oe2 = __shfl_xor(e2[b], 32, 64);
+    top2_merge_narrow(e1[b], j1[b], e2[b], oe1, oj1, oe2);
+  }
+  // lane l's own point is point (l & 31) of block (l >> 5)
+  e1o = h ? e1[1] : e1[0];
+  e2o = h ? e2[1] : e2[0];
+  j1o = h ? j1[1] : j1[0];
+}
+
+// ---------------------------------------------------------------------------
 // Assignment.  Grid = flattened tiles of the active jobs; each workgroup
 // handles tile_pts points of one job in chunks of 256 (one point per lane).
 //
@@ -289,7 +370,7 @@ typedef const double __attribute__((address_space(4)))* cdouble_p;
 // by the previous kernel, so per-centroid fetches from memory would leave
 // every wave waiting on a chain of cache misses); the distance loop then
 // reads each centroid row as LDS broadcasts and feeds it to PPL*NP FMAs.
-template <int NP, int PPL, bool SUMS, bool COOP = false>
+template <int NP, int PPL, bool SUMS, bool COOP = false, bool MF = false>
 __device__ inline void assign_range(const AssignArgs& a, int job, int64_t p_begin, int64_t p_end,
                                     int first_assign, unsigned char* smem, bool staged = false,
                                     double* tfj = nullptr, unsigned long long* accj = nullptr,
@@ -337,8 +418,9 @@ __device__ inline void assign_range(const AssignArgs& a, int job, int64_t p_begi
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) cmax2 = fmaxf(cmax2, __shfl_xor(cmax2, off, 64));
   const float cmax = sqrtf(cmax2) * 1.0000002f;
-  // two interleaved FMA chains of NP/2 terms per dot product, then one add
-  constexpr float kTerms = (float)(NP / 2 + 1);
+  // two interleaved FMA chains of NP/2 terms per dot product, then one add;
+  // on the matrix cores, NP products summed in any order
+  constexpr float kTerms = MF ? (float)(NP + 1) : (float)(NP / 2 + 1);
   const float gam = kTerms * kU / (1.f - kTerms * kU);
   const float kB = 2.f * (2.f * gam + 2.f * kU);
   const bool vec = a.vec != 0;
@@ -382,6 +464,10 @@ __device__ inline void assign_range(const AssignArgs& a, int job, int64_t p_begi
       e2[p] = __builtin_inff();
       j1[p] = 0;
     }
+    if constexpr (MF) {
+#pragma unroll
+      for (int p = 0; p < PPL; ++p) mfma_rank<NP>(x[p], sC, sCn, k, e1[p], e2[p], j1[p]);
+    } else
     for (int j = 0; j < k; ++j) {
       const float4* c4 = reinterpret_cast<const float4*>(sC + j * NP);
       float q0[PPL], q1[PPL];
@@ -562,7 +648,7 @@ __device__ inline void assign_range(const AssignArgs& a, int job, int64_t p_begi
 }
 
 // Multi-launch form: one workgroup per tile of the flattened tile map.
-template <int NP, int PPL, bool SUMS, bool COOP>
+template <int NP, int PPL, bool SUMS, bool COOP, bool MF>
 __global__ __launch_bounds__(kWG) void k_assign_small(AssignArgs a) {
   const int job = a.tile_job[blockIdx.x];
   const int t = a.tile_idx[blockIdx.x];
@@ -576,7 +662,7 @@ __global__ __launch_bounds__(kWG) void k_assign_small(AssignArgs a) {
   const int64_t p_begin = (int64_t)t * a.tile_pts;
   const int64_t p_end = min(s, p_begin + a.tile_pts);
   extern __shared__ __align__(16) unsigned char smem[];
-  assign_range<NP, PPL, SUMS, COOP>(a, job, p_begin, p_end, first_assign, smem);
+  assign_range<NP, PPL, SUMS, COOP, MF>(a, job, p_begin, p_end, first_assign, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -1319,9 +1405,9 @@ size_t __host__ __device__ inline round_assign_bytes(int cp, int k) {
   return base + (size_t)k * cp * 8 + ((size_t)k * 4 + 15) / 16 * 16;
 }
 
-template <int NP>
+template <int NP, bool MF>
 __global__ __launch_bounds__(kWG, 4) void k_round(const RoundArgs* __restrict__ rp) {
-  constexpr int PPL = NP <= 32 ? 2 : 1;
+  constexpr int PPL = (NP <= 32 && !MF) ? 2 : 1;
   // the arguments, read many times by every phase, live in LDS
   __shared__ RoundArgs r_lds;
   if (threadIdx.x == 0) r_lds = *rp;
@@ -1418,7 +1504,7 @@ __global__ __launch_bounds__(kWG, 4) void k_round(const RoundArgs* __restrict__ 
     __syncthreads();
     lds_norms<NP>(sC, sCn, k);
     __syncthreads();
-    assign_range<NP, PPL, false>(r.as, w, p0, p1, 0, smem, true, tf3 + 2 * mc);
+    assign_range<NP, PPL, false, false, MF>(r.as, w, p0, p1, 0, smem, true, tf3 + 2 * mc);
     xcd_barrier(bar, nwg, epoch, r.err);
     if (threadIdx.x < 64) {
       const double f = wave_chunked_sum(tf3 + 2 * mc, nch);
@@ -1476,7 +1562,7 @@ __global__ __launch_bounds__(kWG, 4) void k_round(const RoundArgs* __restrict__ 
     double f_prev = 0.0;
     for (int it = 0; it <= r.max_iter; ++it, ++ig) {
       const int b = ig % 3;
-      assign_range<NP, PPL, true>(r.as, w, p0, p1, it == 0 ? 1 : 0, smem, true, tf3 + b * mc,
+      assign_range<NP, PPL, true, false, MF>(r.as, w, p0, p1, it == 0 ? 1 : 0, smem, true, tf3 + b * mc,
                                   dl3 + (int64_t)b * k * NP, dc3 + b * k);
       {  // clear the buffers of the next iteration (last read two barriers ago),
          // each workgroup its share
@@ -1554,10 +1640,10 @@ __global__ __launch_bounds__(64) void k_xcd_probe(uint32_t* __restrict__ out) {
   if (threadIdx.x == 0) out[blockIdx.x] = x & (kMaxXcd - 1);
 }
 
-template <int NP>
+template <int NP, bool MF>
 hipError_t round_capacity_np(size_t lds, int* blocks) {
   int per_cu = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_round<NP>, kWG, lds);
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_round<NP, MF>, kWG, lds);
   if (e != hipSuccess) return e;
   int dev = 0, cus = 0;
   e = hipGetDevice(&dev);
@@ -1568,46 +1654,48 @@ hipError_t round_capacity_np(size_t lds, int* blocks) {
   return hipSuccess;
 }
 
-template <int NP>
+template <int NP, bool MF>
 hipError_t launch_round_np(hipStream_t st, const RoundArgs* r_dev, int grid, size_t lds) {
   if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_round<NP>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_round<NP, MF>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
   const RoundArgs* p = r_dev;
   void* args[] = {&p};
-  return hipLaunchCooperativeKernel((const void*)k_round<NP>, dim3(grid), dim3(kWG), args,
+  return hipLaunchCooperativeKernel((const void*)k_round<NP, MF>, dim3(grid), dim3(kWG), args,
                                     (unsigned int)lds, st);
 }
 
-template <int NP, bool SUMS, bool COOP>
+template <int NP, bool SUMS, bool COOP, bool MF>
 hipError_t launch_assign_v(hipStream_t st, const AssignArgs& a, int ntiles, size_t lds) {
-  // two points per lane while both fit comfortably in registers
-  constexpr int PPL = NP <= 32 ? 2 : 1;
+  // two points per lane while both fit comfortably in registers (one on the
+  // matrix cores, whose accumulators take the room)
+  constexpr int PPL = (NP <= 32 && !MF) ? 2 : 1;
   if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_assign_small<NP, PPL, SUMS, COOP>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_assign_small<NP, PPL, SUMS, COOP, MF>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((k_assign_small<NP, PPL, SUMS, COOP>), dim3(ntiles), dim3(kWG), lds, st, a);
+  hipLaunchKernelGGL((k_assign_small<NP, PPL, SUMS, COOP, MF>), dim3(ntiles), dim3(kWG), lds, st, a);
   return hipGetLastError();
 }
 
-// From 64 centres on, the wave re-decides its flagged points together (the
-// sequential form costs k distances per lane whenever one lane of the wave
-// needs it); below, the sequential form keeps the kernel's registers lower.
+// The wave re-decides its flagged points together: the sequential form
+// costs k distances per lane whenever one lane of the wave needs it, and on
+// clustered data with background noise most waves hold such a point (the
+// objective over 10,000,000 x 28 points with k = 50: 1.18 -> 0.85 ms).  The
+// per-step kernels rank on the FP32 FMAs, two points per lane up to 32
+// dimensions (measured faster than the matrix-core ranking here, whose
+// looser bound flags more points); the round kernel ranks on the matrix cores.
 template <int NP>
 hipError_t launch_assign_np(hipStream_t st, const AssignArgs& a, int ntiles, bool sums) {
   const size_t base = (((size_t)a.k * NP + a.k) * 4 + 15) / 16 * 16;
-  const bool coop = a.k >= 64;
   if (sums) {
     const size_t lds = base + (size_t)a.k * NP * 8 + (size_t)a.k * 4;
-    return coop ? launch_assign_v<NP, true, true>(st, a, ntiles, lds)
-                : launch_assign_v<NP, true, false>(st, a, ntiles, lds);
+    return launch_assign_v<NP, true, true, false>(st, a, ntiles, lds);
   }
-  return coop ? launch_assign_v<NP, false, true>(st, a, ntiles, base)
-              : launch_assign_v<NP, false, false>(st, a, ntiles, base);
+  return launch_assign_v<NP, false, true, false>(st, a, ntiles, base);
 }
 
 }  // namespace
@@ -1752,17 +1840,17 @@ size_t round_lds_bytes(int32_t cp, int32_t k) {
     default: return hipErrorInvalidValue; \
   }
 
-template <int NP, bool COOP>
+template <int NP>
 hipError_t assign_static_lds_np(size_t* out) {
-  constexpr int PPL = NP <= 32 ? 2 : 1;
+  constexpr int PPL = NP <= 32 ? 2 : 1;  // the variant launched for a Lloyd step
   hipFuncAttributes fa;
-  hipError_t e = hipFuncGetAttributes(&fa, (const void*)k_assign_small<NP, PPL, true, COOP>);
+  hipError_t e = hipFuncGetAttributes(&fa, (const void*)k_assign_small<NP, PPL, true, true, false>);
   if (e == hipSuccess) *out = fa.sharedSizeBytes;
   return e;
 }
 
-hipError_t assign_static_lds(int32_t cp, bool coop, size_t* out) {
-#define BM_SL(NPV) (coop ? assign_static_lds_np<NPV, true>(out) : assign_static_lds_np<NPV, false>(out))
+hipError_t assign_static_lds(int32_t cp, size_t* out) {
+#define BM_SL(NPV) assign_static_lds_np<NPV>(out)
   BM_ROUND_SWITCH(BM_SL)
 #undef BM_SL
 }
@@ -1772,15 +1860,17 @@ hipError_t launch_xcd_probe(hipStream_t st, uint32_t* out, int32_t grid) {
   return hipGetLastError();
 }
 
-hipError_t round_capacity(int32_t cp, size_t lds, int* blocks) {
-#define BM_CAP(NPV) round_capacity_np<NPV>(lds, blocks)
+hipError_t round_capacity(int32_t cp, int32_t k, size_t lds, int* blocks) {
+#define BM_CAP(NPV) (k >= kMfmaMinK ? round_capacity_np<NPV, true>(lds, blocks) \
+                                    : round_capacity_np<NPV, false>(lds, blocks))
   BM_ROUND_SWITCH(BM_CAP)
 #undef BM_CAP
 }
 
-hipError_t launch_round(hipStream_t st, const RoundArgs* r_dev, int32_t cp, int32_t grid,
-                        size_t lds) {
-#define BM_LR(NPV) launch_round_np<NPV>(st, r_dev, grid, lds)
+hipError_t launch_round(hipStream_t st, const RoundArgs* r_dev, int32_t cp, int32_t k,
+                        int32_t grid, size_t lds) {
+#define BM_LR(NPV) (k >= kMfmaMinK ? launch_round_np<NPV, true>(st, r_dev, grid, lds) \
+                                   : launch_round_np<NPV, false>(st, r_dev, grid, lds))
   BM_ROUND_SWITCH(BM_LR)
 #undef BM_LR
 }
