@@ -49,15 +49,14 @@ __device__ inline double wave_chunked_sum(const double* __restrict__ v, int64_t 
   const int64_t cs = (cnt + 63) / 64;
   const int64_t lo = min(cnt, (int64_t)lane * cs), hi = min(cnt, lo + cs);
   double tot = 0.0;
-  if (cs <= 4) {  // loads issued together, added in the same order
-    double t[4];
+  // eight loads issued together, added in index order
+  for (int64_t q0 = lo; q0 < hi; q0 += 8) {
+    double t[8];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) t[q] = lo + q < hi ? v[lo + q] : 0.0;
+    for (int q = 0; q < 8; ++q) t[q] = q0 + q < hi ? v[q0 + q] : 0.0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (lo + q < hi) tot += t[q];
-  } else {
-    for (int64_t q = lo; q < hi; ++q) tot += v[q];
+    for (int q = 0; q < 8; ++q)
+      if (q0 + q < hi) tot += t[q];
   }
   return wave_ordered_sum(tot);
 }

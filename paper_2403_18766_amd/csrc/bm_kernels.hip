@@ -897,31 +897,38 @@ __global__ __launch_bounds__(kWG) void k_kpp_init(KppArgs a) {
   kpp_init_tile(a, kpp_job(a, blockIdx.y), blockIdx.x);
 }
 
-// Wave-level monotone prefix over v[0..cnt): lane l sums a contiguous chunk
-// sequentially; the lane carries are a sequential sum of the chunk totals.
-// Returns the total (uniform).  If tau >= 0 is given, *first receives the
-// first index whose running prefix exceeds tau (or -1) and *before the
-// prefix just before it.
-template <typename T>
-__device__ inline double wave_prefix_search(const T* v, int64_t cnt, double tau, int64_t* first,
-                                            double* before) {
+// Wave-level monotone prefix over v[0..cnt): lane l sums the contiguous chunk
+// [l * cs, (l + 1) * cs) in index order (cs = ceil(cnt / 64)); the lane
+// carries are a sequential sum of the chunk totals in lane order.  Returns the
+// total (the same in every lane).  For each of the first nt thresholds
+// tau[0..2], first[t] receives the first index whose running prefix exceeds
+// tau[t] (or -1) and before[t] the prefix just before it.  A chunk of at most
+// PRE values is loaded at once and kept in registers for every threshold;
+// longer chunks are read PRE values at a time, once per pass.
+template <typename T, int PRE>
+__device__ inline double wave_prefix_multi(const T* v, int64_t cnt, int nt, const double (&tau)[3],
+                                           int64_t (&first)[3], double (&before)[3]) {
   const int lane = threadIdx.x & 63;
   const int64_t cs = (cnt + 63) / 64;
   const int64_t lo = min(cnt, (int64_t)lane * cs), hi = min(cnt, lo + cs);
-  // up to 4 values per lane are loaded together and kept for the search
-  T pre[4];
-  const bool few = cs <= 4;
-  if (few) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) pre[q] = lo + q < hi ? v[lo + q] : (T)0;
-  }
+  const bool held = cs <= PRE;
+  T pre[PRE];
   double tot = 0.0;
-  if (few) {
+  if (held) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < PRE; ++q) pre[q] = lo + q < hi ? v[lo + q] : (T)0;
+#pragma unroll
+    for (int q = 0; q < PRE; ++q)
       if (lo + q < hi) tot += (double)pre[q];
   } else {
-    for (int64_t q = lo; q < hi; ++q) tot += (double)v[q];
+    for (int64_t q0 = lo; q0 < hi; q0 += PRE) {
+      T b[PRE];
+#pragma unroll
+      for (int u = 0; u < PRE; ++u) b[u] = q0 + u < hi ? v[q0 + u] : (T)0;
+#pragma unroll
+      for (int u = 0; u < PRE; ++u)
+        if (q0 + u < hi) tot += (double)b[u];
+    }
   }
   double carry = 0.0, total = 0.0;
 #pragma unroll 8
@@ -930,52 +937,82 @@ __device__ inline double wave_prefix_search(const T* v, int64_t cnt, double tau,
     if (l == lane) carry = total;
     total += tl;
   }
-  if (first) {
-    int64_t found = -1;
-    double bef = 0.0;
-    double r = carry;
-    if (few) {
+  if (nt <= 0) return total;
+  // one running prefix, compared with every threshold
+  int64_t found[3] = {-1, -1, -1};
+  double bef[3] = {0.0, 0.0, 0.0};
+  double r = carry;
+  if (held) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (found < 0 && lo + q < hi) {
-          const double prev = r;
-          r += (double)pre[q];
-          if (r > tau) {
-            found = lo + q;
-            bef = prev;
+    for (int q = 0; q < PRE; ++q) {
+      if (lo + q < hi) {
+        const double prev = r;
+        r += (double)pre[q];
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+          if (t < nt && found[t] < 0 && r > tau[t]) {
+            found[t] = lo + q;
+            bef[t] = prev;
           }
         }
       }
-    } else {
-      for (int64_t q = lo; q < hi; ++q) {
-        const double prev = r;
-        r += (double)v[q];
-        if (r > tau) {
-          found = q;
-          bef = prev;
-          break;
+    }
+  } else {
+    for (int64_t q0 = lo; q0 < hi; q0 += PRE) {
+      T b[PRE];
+#pragma unroll
+      for (int u = 0; u < PRE; ++u) b[u] = q0 + u < hi ? v[q0 + u] : (T)0;
+#pragma unroll
+      for (int u = 0; u < PRE; ++u) {
+        if (q0 + u < hi) {
+          const double prev = r;
+          r += (double)b[u];
+#pragma unroll
+          for (int t = 0; t < 3; ++t) {
+            if (t < nt && found[t] < 0 && r > tau[t]) {
+              found[t] = q0 + u;
+              bef[t] = prev;
+            }
+          }
         }
       }
     }
-    // smallest lane that found a crossing
-    int64_t best = found >= 0 ? found : INT64_MAX;
-    double bbef = bef;
-    for (int off = 32; off > 0; off >>= 1) {
-      const int64_t ob = __shfl_xor(best, off, 64);
-      const double obf = __shfl_xor(bbef, off, 64);
-      if (ob < best) {
-        best = ob;
-        bbef = obf;
+  }
+  // per threshold, the smallest index found by any lane
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    if (t < nt) {
+      int64_t best = found[t] >= 0 ? found[t] : INT64_MAX;
+      double bbef = bef[t];
+      for (int off = 32; off > 0; off >>= 1) {
+        const int64_t ob = __shfl_xor(best, off, 64);
+        const double obf = __shfl_xor(bbef, off, 64);
+        if (ob < best) {
+          best = ob;
+          bbef = obf;
+        }
       }
+      first[t] = best == INT64_MAX ? -1 : best;
+      before[t] = bbef;
     }
-    *first = best == INT64_MAX ? -1 : best;
-    *before = bbef;
   }
   return total;
 }
 
+// Total of v[0..cnt) in the order of wave_prefix_multi.
+template <typename T, int PRE>
+__device__ inline double wave_prefix_total(const T* v, int64_t cnt) {
+  const double none[3] = {0.0, 0.0, 0.0};
+  int64_t f[3];
+  double b[3];
+  return wave_prefix_multi<T, PRE>(v, cnt, 0, none, f, b);
+}
+
 // One wave per job: commit the pending step, then draw the next one (scans
 // and searches are wave-level; lane = threadIdx.x, which must be < 64).
+// PRE values per lane of a tile-sum scan are held in registers (see
+// wave_prefix_multi): the scan then costs one round trip to memory.
+template <int PRE>
 __device__ __noinline__ void kpp_step_job(const KppArgs& a, int job) {
   KppState ks = a.ks[job];
   const int64_t s = a.s[job];
@@ -986,8 +1023,7 @@ __device__ __noinline__ void kpp_step_job(const KppArgs& a, int job) {
   if (ks.ncand > 0) {
     for (int c = 0; c < ks.ncand; ++c) {
       const int sl = other_slot(ks.dcur, c);
-      ks.pot[c] = wave_prefix_search<double>(a.Dt + ((int64_t)sl * a.njobs + job) * a.ndt_max,
-                                             ndt, -1.0, nullptr, nullptr);
+      ks.pot[c] = wave_prefix_total<double, PRE>(a.Dt + ((int64_t)sl * a.njobs + job) * a.ndt_max, ndt);
     }
     int best = 0;
     for (int c = 1; c < ks.ncand; ++c)
@@ -1015,47 +1051,94 @@ __device__ __noinline__ void kpp_step_job(const KppArgs& a, int job) {
     const uint64_t g = a.gs ? a.gs[job] : a.g;
     const U64x4 w = philox_ctr((uint64_t)ks.step, g, 0, 0, k0, k1);
     const double* dt = a.Dt + ((int64_t)ks.dcur * a.njobs + job) * a.ndt_max;
-    if (ks.has_d && ks.step == 0) ks.T = wave_prefix_search<double>(dt, ndt, -1.0, nullptr, nullptr);
+    if (ks.has_d && ks.step == 0) ks.T = wave_prefix_total<double, PRE>(dt, ndt);
     if (!ks.has_d || !(ks.T > 0.0 && ks.T < __builtin_inf())) {
       ks.ncand = 1;
       ks.uniform = 1;
       ks.cand[0] = (int32_t)bounded(w.w[3], (uint64_t)s);
       ks.cand[1] = ks.cand[2] = -1;
     } else {
-      ks.ncand = a.n_cand;
+      const int nc = a.n_cand;
+      ks.ncand = nc;
       ks.uniform = 0;
       const float* Dj = a.D + (int64_t)ks.dcur * a.D_slot_stride + job * a.D_job_stride;
-      for (int c = 0; c < a.n_cand; ++c) {
-        const double tau = u01(w.w[c]) * ks.T;
-        int64_t tile;
-        double base;
-        wave_prefix_search<double>(dt, ndt, tau, &tile, &base);
-        if (tile < 0) {  // rounding put tau at the very end: last tile with mass,
-          tile = ndt - 1;  // whose first point with D > 0 is taken below
-          while (tile > 0 && !(dt[tile] > 0.0)) --tile;
-          base = tau;
+      // the tiles of all candidates in one scan of the tile sums
+      const double tau[3] = {u01(w.w[0]) * ks.T, u01(w.w[1]) * ks.T, u01(w.w[2]) * ks.T};
+      int64_t tile[3];
+      double base[3];
+      wave_prefix_multi<double, PRE>(dt, ndt, nc, tau, tile, base);
+      // then the points inside those tiles (at most 256 each: four per lane),
+      // all loaded before the searches
+      int64_t lo[3], cnt[3];
+      double tin[3];
+      float held[3][4];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        lo[c] = 0;
+        cnt[c] = 0;
+        tin[c] = 0.0;
+        if (c < nc) {
+          if (tile[c] < 0) {  // rounding put tau at the very end: last tile with
+            int64_t t = ndt - 1;  // mass, whose first point with D > 0 is taken below
+            while (t > 0 && !(dt[t] > 0.0)) --t;
+            tile[c] = t;
+            base[c] = tau[c];
+          }
+          lo[c] = tile[c] * kDTile;
+          cnt[c] = min((int64_t)kDTile, s - lo[c]);
+          // running prefix inside the tile, started at the tile's base
+          tin[c] = tau[c] - base[c];
         }
-        const int64_t lo = tile * kDTile;
-        const int64_t cnt = min((int64_t)kDTile, s - lo);
-        int64_t within;
-        double bef;
-        // running prefix inside the tile, started at the tile's base
-        const double tin = tau - base;
-        wave_prefix_search<float>(Dj + lo, cnt, tin, &within, &bef);
-        if (within < 0) {  // fallback: last point of the tile with D > 0
-          within = cnt - 1;
-          while (within > 0 && !(Dj[lo + within] > 0.f)) --within;
-        }
-        ks.cand[c] = (int32_t)(lo + within);
+        const int64_t cs = (cnt[c] + 63) / 64;
+        const int64_t l0 = min(cnt[c], (int64_t)lane * cs), l1 = min(cnt[c], l0 + cs);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) held[c][q] = l0 + q < l1 ? Dj[lo[c] + l0 + q] : 0.f;
       }
-      for (int c = a.n_cand; c < 3; ++c) ks.cand[c] = -1;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (c < nc) {
+          const int64_t cs = (cnt[c] + 63) / 64;
+          const int64_t l0 = min(cnt[c], (int64_t)lane * cs), l1 = min(cnt[c], l0 + cs);
+          double tot = 0.0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (l0 + q < l1) tot += (double)held[c][q];
+          double carry = 0.0, total = 0.0;
+#pragma unroll 8
+          for (int l = 0; l < 64; ++l) {
+            const double tl = lane_value(tot, l);
+            if (l == lane) carry = total;
+            total += tl;
+          }
+          int64_t found = -1;
+          double r = carry;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            if (found < 0 && l0 + q < l1) {
+              r += (double)held[c][q];
+              if (r > tin[c]) found = l0 + q;
+            }
+          }
+          int64_t within = found >= 0 ? found : INT64_MAX;
+          for (int off = 32; off > 0; off >>= 1) within = min(within, __shfl_xor(within, off, 64));
+          if (within == INT64_MAX) {  // fallback: last point of the tile with D > 0
+            within = cnt[c] - 1;
+            while (within > 0 && !(Dj[lo[c] + within] > 0.f)) --within;
+          }
+          ks.cand[c] = (int32_t)(lo[c] + within);
+        } else {
+          ks.cand[c] = -1;
+        }
+      }
     }
     ks.step += 1;
   }
   if (lane == 0) a.ks[job] = ks;
 }
 
-__global__ __launch_bounds__(64) void k_kpp_step(KppArgs a) { kpp_step_job(a, kpp_job(a, blockIdx.x)); }
+__global__ __launch_bounds__(64) void k_kpp_step(KppArgs a) {
+  kpp_step_job<16>(a, kpp_job(a, blockIdx.x));
+}
 
 // Potentials of the pending candidates: new D per candidate into the other
 // slots, with per-tile sums.
@@ -1241,22 +1324,20 @@ __device__ inline double load_dev(const double* p) {
   return __longlong_as_double((long long)load_dev(reinterpret_cast<const unsigned long long*>(p)));
 }
 
-// wave_chunked_sum through device-scope loads (same order, same result).  Up
-// to 4 values per lane (256 chunks) are loaded together before they are added.
+// wave_chunked_sum through device-scope loads (same order, same result):
+// eight values per lane are loaded together before they are added.
 __device__ inline double wave_chunked_sum_dev(const double* v, int64_t cnt) {
   const int lane = threadIdx.x & 63;
   const int64_t cs = (cnt + 63) / 64;
   const int64_t lo = min(cnt, (int64_t)lane * cs), hi = min(cnt, lo + cs);
   double tot = 0.0;
-  if (cs <= 4) {
-    double t[4];
+  for (int64_t q0 = lo; q0 < hi; q0 += 8) {
+    double t[8];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) t[q] = lo + q < hi ? load_dev(v + lo + q) : 0.0;
+    for (int q = 0; q < 8; ++q) t[q] = q0 + q < hi ? load_dev(v + q0 + q) : 0.0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (lo + q < hi) tot += t[q];
-  } else {
-    for (int64_t q = lo; q < hi; ++q) tot += load_dev(v + q);
+    for (int q = 0; q < 8; ++q)
+      if (q0 + q < hi) tot += t[q];
   }
   return wave_ordered_sum(tot);
 }
@@ -1540,12 +1621,12 @@ __global__ __launch_bounds__(kWG, 4) void k_round(const RoundArgs* __restrict__ 
       kpp_init_range<NP>(ka, w, c0, c1, sI, sIdeg, kred);
       xcd_barrier(bar, nwg, epoch, r.err);
       for (int step = 0; step < ntodo; ++step) {
-        if (leader && threadIdx.x < 64) kpp_step_job(ka, w);
+        if (leader && threadIdx.x < 64) kpp_step_job<4>(ka, w);
         xcd_barrier(bar, nwg, epoch, r.err);
         kpp_pot_range<NP>(ka, w, c0, c1, krows, kred);
         xcd_barrier(bar, nwg, epoch, r.err);
       }
-      if (leader && threadIdx.x < 64) kpp_step_job(ka, w);  // commits the last step
+      if (leader && threadIdx.x < 64) kpp_step_job<4>(ka, w);  // commits the last step
       xcd_barrier(bar, nwg, epoch, r.err);
       const float* Cp = r.Cp + (int64_t)w * k * NP;
       for (int e = threadIdx.x; e < k * NP; e += kWG) sC[e] = Cp[e];
@@ -1579,7 +1660,18 @@ __global__ __launch_bounds__(kWG, 4) void k_round(const RoundArgs* __restrict__ 
       }
       xcd_barrier(bar, nwg, epoch, r.err, false);
       // every arrival's atomics and stores are complete in L2
-      for (int e = threadIdx.x; e < k * NP; e += kWG) tot[e] += (long long)load_dev(dl3 + (int64_t)b * k * NP + e);
+      {  // eight loads in flight per thread (integer sums: any order)
+        const unsigned long long* src = dl3 + (int64_t)b * k * NP;
+        const int tot_e = k * NP;
+        for (int e0 = threadIdx.x; e0 < tot_e; e0 += 8 * kWG) {
+          unsigned long long t8[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) t8[u] = e0 + u * kWG < tot_e ? load_dev(src + e0 + u * kWG) : 0ull;
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (e0 + u * kWG < tot_e) tot[e0 + u * kWG] += (long long)t8[u];
+        }
+      }
       for (int j = threadIdx.x; j < k; j += kWG) tcnt[j] += load_dev(dc3 + b * k + j);
       if (threadIdx.x < 64) {
         const double f = wave_chunked_sum_dev(tf3 + b * mc, nch);

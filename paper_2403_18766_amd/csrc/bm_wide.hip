@@ -56,6 +56,7 @@ constexpr int kCG = 128;           // centres per group (four 32-wide MFMA tiles
 constexpr int kChunk = 256;        // points per chunk (one per thread in the per-point phase)
 constexpr int kUpdDims = 64;       // dimensions per update workgroup
 constexpr int kUpdPts = 8192;      // points per update workgroup
+constexpr int kUpdBatch = 16;      // changed points whose slices load together
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -840,21 +841,32 @@ __global__ __launch_bounds__(256) void k_update_wide(UpdateArgs u) {
     unsigned long long pend = __ballot(i < r1 && jn != jo);
     if (pend) changed = 1;
     while (pend) {
-      const int src = __ffsll(pend) - 1;
-      pend &= pend - 1;
-      const int pn = __builtin_amdgcn_readlane(jn, src);
-      const int po = __builtin_amdgcn_readlane(jo, src);
-      if (lane < nd) {
-        const float xv = S[(i0 + src) * (int64_t)u.ld + d0 + lane];
-        const long long qv = quantize(xv, sc);
-        if (qv != 0) {
+      // up to kUpdBatch changed points at a time: their slices are loaded
+      // together, then added (integer sums: the order does not matter)
+      int src[kUpdBatch];
+#pragma unroll
+      for (int t = 0; t < kUpdBatch; ++t) {
+        src[t] = pend ? __ffsll(pend) - 1 : -1;
+        pend &= pend - 1;
+      }
+      float xv[kUpdBatch];
+#pragma unroll
+      for (int t = 0; t < kUpdBatch; ++t)
+        xv[t] = (src[t] >= 0 && lane < nd) ? S[(i0 + src[t]) * (int64_t)u.ld + d0 + lane] : 0.f;
+#pragma unroll
+      for (int t = 0; t < kUpdBatch; ++t) {
+        if (src[t] < 0) break;
+        const int pn = __builtin_amdgcn_readlane(jn, src[t]);
+        const int po = __builtin_amdgcn_readlane(jo, src[t]);
+        const long long qv = quantize(xv[t], sc);
+        if (lane < nd && qv != 0) {
           atomicAdd(&lacc[pn * kUpdDims + lane], (unsigned long long)qv);
           if (po >= 0) atomicAdd(&lacc[po * kUpdDims + lane], (unsigned long long)(-qv));
         }
-      }
-      if (counts && lane == 0) {
-        atomicAdd(&lcnt[pn], 1);
-        if (po >= 0) atomicAdd(&lcnt[po], -1);
+        if (counts && lane == 0) {
+          atomicAdd(&lcnt[pn], 1);
+          if (po >= 0) atomicAdd(&lcnt[po], -1);
+        }
       }
     }
   }
