@@ -321,7 +321,7 @@ def serve_run(torch, dev, njobs):
             "peak_bytes": st["peak_bytes"], "slot_bytes": st["slot_bytes"]}
 
 
-PREC = dict(m=2_000_000, n=768, k=100, workers=16, s=131_072, rounds_T=2, passes_p=10)
+PREC = dict(m=2_000_000, n=768, k=100, workers=16, s=131_072, rounds_T=2, passes_p=1)
 
 
 def precision_run(torch, dev):

@@ -28,7 +28,7 @@ CONFIGS = {
                     size_policy=obm.SIZE_LOGUNIFORM, seed=0),
     "noisy28": dict(k=50, workers=64, rounds_T=100, passes_p=10, s_min=1 << 12, s_max=1 << 17,
                     size_policy=obm.SIZE_BINS, seed=0),
-    "vmf768": dict(k=100, workers=16, rounds_T=2, passes_p=10, s_min=131_072, s_max=131_072,
+    "vmf768": dict(k=100, workers=16, rounds_T=2, passes_p=1, s_min=131_072, s_max=131_072,
                    size_policy=obm.SIZE_FIXED, seed=0),
 }
 # large inputs are identified by the chunked digest

@@ -8,10 +8,16 @@ the labels of sampled points.
   * noisy28: 10,000,000 points in 28-D, k = 50, 64 workers with BINS sizes in
     [2^12, 2^17] (one persistent launch per round);
   * serving: the three resident 4,000,000-point data sets (n = 16, 64, 256)
-    with a slice of the job stream; each result is the same served alone.
+    with a slice of the job stream; each result is the same served alone;
+  * Algorithm 1 against the oracle's own Algorithm-1 result on the same data
+    (tests/golden/<workload>_reference.json, written by make_reference.py):
+    noisy28 with all 100 rounds, vmf768 in both precisions, f(C_best, X)
+    within 1 %.
 """
 
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -69,10 +75,15 @@ def test_vmf768_full_size_both_precisions(dev, api):
     assert abs(runs[1]["f_full"] - fo) <= 0.01 * fo
 
 
-def test_noisy28_full_size_persistent_rounds(dev, api):
+@pytest.fixture(scope="module")
+def noisy28_host():
+    say("noisy28 full size: generating 10,000,000 x 28 on the host")
+    return datagen.make("noisy28")
+
+
+def test_noisy28_full_size_persistent_rounds(dev, api, noisy28_host):
     from paper_2403_18766_amd import _lib
-    say("noisy28 full size: generating 10,000,000 x 28")
-    Xh = datagen.make("noisy28")
+    Xh = noisy28_host
     X = to_dev(Xh, dev)
     P = api.RunParams(k=50, workers=64, rounds_T=3, passes_p=10, s_min=1 << 12, s_max=1 << 17,
                       size_policy=_lib.BM_SIZE_BINS, seed=0, batched=1)
@@ -108,3 +119,55 @@ def test_serving_full_size_datasets_alone_equals_mix(dev, api):
         assert math.isfinite(q["f"])
         if q["accepted"]:
             assert q["f_incumbent"] == q["f"]
+
+
+def _reference(name):
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        f"{name}_reference.json")
+    if not os.path.exists(path):
+        pytest.skip(f"no oracle reference for {name}")
+    with open(path) as f:
+        return json.load(f)
+
+
+def _params_of(api, ref, **kw):
+    c = ref["params"]
+    return api.RunParams(k=c["k"], workers=c["workers"], rounds_T=c["rounds_T"],
+                         passes_p=c["passes_p"], s_min=c["s_min"], s_max=c["s_max"],
+                         size_policy=c["size_policy"], max_iter=c.get("max_iter", 300),
+                         tol=c.get("tol", 1e-4), n_candidates=c.get("n_candidates", 3),
+                         seed=c["seed"], **kw)
+
+
+def test_noisy28_algorithm1_within_1pct_of_oracle(dev, api, noisy28_host):
+    """The whole competitive run (64 workers, BINS sizes, 100 rounds, the final
+    stage's selection) against the oracle's Algorithm-1 run on the same data."""
+    ref = _reference("noisy28")
+    assert datagen.sha256_chunked(noisy28_host) == ref["x_sha256_chunked"]
+    X = to_dev(noisy28_host, dev)
+    say("noisy28 Algorithm 1,", ref["params"]["rounds_T"], "rounds, persistent rounds")
+    g = api.bigmeans_run(X, _params_of(api, ref, batched=1), labels=False)
+    gap = (g["f_full"] - ref["f_full"]) / ref["f_full"]
+    say("noisy28 f", g["f_full"], "oracle", ref["f_full"], "gap", gap)
+    assert abs(gap) <= 0.01
+    assert ref["params"]["s_min"] <= g["s_opt"] <= ref["params"]["s_max"]
+
+
+def test_vmf768_algorithm1_within_1pct_of_oracle_both_precisions(dev, api):
+    ref = _reference("vmf768")
+    say("vmf768: generating 2,000,000 x 768 on the host")
+    Xh = datagen.make("vmf768")
+    assert datagen.sha256_chunked(Xh) == ref["x_sha256_chunked"]
+    X = to_dev(Xh, dev)
+    del Xh
+    runs = {}
+    for prec in (0, 1):
+        say("vmf768 Algorithm 1, prec", prec)
+        g = api.bigmeans_run(X, _params_of(api, ref, batched=2, prec=prec), labels=False)
+        runs[prec] = g
+        gap = (g["f_full"] - ref["f_full"]) / ref["f_full"]
+        say("vmf768 prec", prec, "f", g["f_full"], "oracle", ref["f_full"], "gap", gap)
+        assert abs(gap) <= 0.01
+    # equal centroids (the certified labels coincide) give equal objectives
+    if np.array_equal(runs[0]["C_best"].cpu().numpy(), runs[1]["C_best"].cpu().numpy()):
+        assert runs[0]["f_full"] == runs[1]["f_full"]
