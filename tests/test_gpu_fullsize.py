@@ -8,7 +8,8 @@ the labels of sampled points.
   * noisy28: 10,000,000 points in 28-D, k = 50, 64 workers with BINS sizes in
     [2^12, 2^17] (one persistent launch per round);
   * serving: the three resident 4,000,000-point data sets (n = 16, 64, 256)
-    with a slice of the job stream; each result is the same served alone;
+    with a slice of the job stream; each result is the same served alone, and
+    each worker's chain matches the oracle's chain of single passes;
   * Algorithm 1 against the oracle's own Algorithm-1 result on the same data
     (tests/golden/<workload>_reference.json, written by make_reference.py):
     noisy28 with all 100 rounds, vmf768 in both precisions, f(C_best, X)
@@ -99,9 +100,14 @@ def test_noisy28_full_size_persistent_rounds(dev, api, noisy28_host):
     assert np.array_equal(g2["C_best"].cpu().numpy(), g["C_best"].cpu().numpy())
 
 
-def test_serving_full_size_datasets_alone_equals_mix(dev, api):
-    say("serving full size: generating three 4,000,000-point data sets")
-    Xs = [to_dev(datagen.serving_dataset(n, m=4_000_000), dev) for n in (16, 64, 256)]
+@pytest.fixture(scope="module")
+def serving_host():
+    say("serving full size: generating three 4,000,000-point data sets on the host")
+    return [datagen.serving_dataset(n, m=4_000_000) for n in (16, 64, 256)]
+
+
+def test_serving_full_size_datasets_alone_equals_mix(dev, api, serving_host):
+    Xs = [to_dev(X, dev) for X in serving_host]
     r = np.random.default_rng(0)
     jobs = []
     for _ in range(60):
@@ -119,6 +125,44 @@ def test_serving_full_size_datasets_alone_equals_mix(dev, api):
         assert math.isfinite(q["f"])
         if q["accepted"]:
             assert q["f_incumbent"] == q["f"]
+
+
+def test_serving_full_size_matches_oracle_chains(dev, api, serving_host):
+    """A slice of the serving job stream on the three 4,000,000-point data sets
+    (FP32 and BF16 jobs, k in {10, 50}, samples up to 8,192 points so that the
+    FP64 replay stays short): every worker's chain of jobs is replayed with the
+    oracle's single passes of Algorithm 1 on the same data."""
+    from oracle import bigmeans as obm
+    Xd = [to_dev(X, dev) for X in serving_host]
+    r = np.random.default_rng(7)
+    jobs = []
+    for _ in range(18):
+        s = int(math.floor(math.exp(r.uniform(math.log(1024), math.log(8193)))))
+        jobs.append(dict(s=min(s, 8192), dataset=int(r.integers(3)), k=int(r.choice([10, 50])),
+                         worker=int(r.integers(2)), prec=int(r.integers(2))))
+    say("serving full size vs oracle:", len(jobs), "jobs")
+    res, _ = api.serve(Xd, jobs, seed=11, max_slots=16)
+    state = {}
+    same_iters = 0
+    for j, jb in enumerate(jobs):  # equal arrival times: list order
+        key = (jb["dataset"], jb["k"], jb["worker"])
+        X = serving_host[jb["dataset"]]
+        if key not in state:
+            state[key] = dict(C=np.zeros((jb["k"], X.shape[1])), deg=np.ones(jb["k"], bool),
+                              fhat=math.inf, s_prev=None, g=0)
+        S = state[key]
+        wid = (jb["dataset"] << 20) | (jb["k"] << 10) | jb["worker"]
+        say("oracle replay job", j, "n", X.shape[1], "k", jb["k"], "s", jb["s"])
+        o = obm.worker_pass(X, S["C"], S["deg"], S["fhat"], S["s_prev"], jb["s"], 11, wid,
+                            S["g"], S["g"], 3, 300, 1e-4)
+        S.update(C=o["C"], deg=o["deg"], fhat=o["fhat"], s_prev=jb["s"], g=S["g"] + 1)
+        g = res[j]
+        if g["iters"] == o["iters"]:
+            same_iters += 1
+            assert abs(g["f"] - o["f"]) <= 1e-5 * abs(o["f"]), (j, g["f"], o["f"])
+        assert g["accepted"] == o["accepted"] or abs(g["f"] - g["f_incumbent"]) <= 1e-5 * g["f"]
+        assert abs(g["f_incumbent"] - o["fhat"]) <= 0.01 * o["fhat"], (j, g, o["fhat"])
+    assert same_iters >= 0.8 * len(jobs)
 
 
 def _reference(name):

@@ -154,8 +154,11 @@ def test_lloyd_wide_deterministic(dev, api):
 
 
 def test_kmeanspp_wide_valid(dev, api):
-    # every pick is a sample row; the seeded centres' potential is within the
-    # oracle K-means++ range on the same sample (greedy, 3 candidates)
+    # all centroids degenerate: every pick is a sample row, every step's
+    # candidates are the oracle's draws from its own D (built from the GPU's
+    # earlier choices) and the kept candidate has the smallest potential; the
+    # seeded centres' potential is within the oracle K-means++ range
+    from tests.test_gpu_parity import _replay_kmeanspp
     S = datagen.make("vmf768", m=4_000, seed=3)
     k = 20
     C = np.zeros((k, S.shape[1]), np.float32)
@@ -166,6 +169,8 @@ def test_kmeanspp_wide_valid(dev, api):
     assert dg.cpu().numpy().sum() == 0
     assert np.array_equal(Cg.cpu().numpy(), S[picks[:, 0]])
     assert len(set(picks[:, 0].tolist())) == k
+    exact, steps = _replay_kmeanspp(S, C, deg.astype(bool), picks, 3, 1, 0, 0)
+    assert steps == k and exact >= steps - 1
     Co, _, _ = okm.kmeanspp(S, C, deg.astype(bool), 3, 1, 0, 0)
     fg = okm.objective(S, Cg.cpu().numpy())
     fo = okm.objective(S, Co)
