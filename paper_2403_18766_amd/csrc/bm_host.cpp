@@ -871,11 +871,13 @@ int round_persistent(bm_ctx* c, const float* X, const bm_params& p, int t,
     }
   }
   const int64_t mc = c->max_chunks;
-  // work buffer: [reg kMaxXcd][grid barrier][W barriers][delta W*3*k*cp][dcnt W*3*k] | [tf3 W*3*mc]
+  // work buffer: [reg kMaxXcd][grid barrier][W barriers][delta W*3*k*cp][dcnt W*3*k]
+  //              [claim W*3] | [tf3 W*3*mc]; zero up to tf3
   const size_t off_gbar = 64, off_bar = 128;
   const size_t off_delta = off_bar + (size_t)W * sizeof(bm::GroupBar);
   const size_t off_dcnt = off_delta + (size_t)W * 3 * k * cp * sizeof(unsigned long long);
-  const size_t off_tf3 = (off_dcnt + (size_t)W * 3 * k * sizeof(int32_t) + 255) / 256 * 256;
+  const size_t off_claim = off_dcnt + (size_t)W * 3 * k * sizeof(int32_t);
+  const size_t off_tf3 = (off_claim + (size_t)W * 3 * sizeof(unsigned int) + 255) / 256 * 256;
   const size_t work_bytes = off_tf3 + (size_t)W * 3 * mc * sizeof(double);
   const size_t map_bytes = (size_t)bm::kMaxXcd * (2 * W + 1) * sizeof(int32_t);
   const size_t rres_bytes = 16 + (size_t)W * sizeof(double) + (size_t)W * p.passes_p * sizeof(bm::PassOut);
@@ -920,6 +922,7 @@ int round_persistent(bm_ctx* c, const float* X, const bm_params& p, int t,
   r.bar = reinterpret_cast<bm::GroupBar*>(wk + off_bar);
   r.delta = reinterpret_cast<unsigned long long*>(wk + off_delta);
   r.dcnt = reinterpret_cast<int32_t*>(wk + off_dcnt);
+  r.claim = reinterpret_cast<unsigned int*>(wk + off_claim);
   r.tf3 = reinterpret_cast<double*>(wk + off_tf3);
   bm::AssignArgs& a = r.as;
   a.S = P<float>(c->S);

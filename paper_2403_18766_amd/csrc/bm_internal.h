@@ -205,6 +205,7 @@ struct RoundArgs {
   KppArgs ka;                  // job = worker
   unsigned long long* delta;   // [W][3][k*cp] fixed-point sum deltas (zero at launch)
   int32_t* dcnt;               // [W][3][k] count deltas (zero at launch)
+  unsigned int* claim;         // [W][3] Lloyd assignment units claimed (zero at launch)
   double* tf3;                 // [W][3][max_chunks] chunk objective partials
   const double* inv_scale;     // [cp]
   float* Cinc;                 // [W][k][n] incumbents

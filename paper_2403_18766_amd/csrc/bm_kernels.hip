@@ -374,7 +374,8 @@ template <int NP, int PPL, bool SUMS, bool COOP = false, bool MF = false>
 __device__ inline void assign_range(const AssignArgs& a, int job, int64_t p_begin, int64_t p_end,
                                     int first_assign, unsigned char* smem, bool staged = false,
                                     double* tfj = nullptr, unsigned long long* accj = nullptr,
-                                    int32_t* cntj = nullptr) {
+                                    int32_t* cntj = nullptr, unsigned int* claim = nullptr,
+                                    int first_unit = 0, int claim_base = 0) {
   if (tfj == nullptr) tfj = a.tf + (int64_t)job * a.max_chunks;
   if (SUMS && accj == nullptr) {
     accj = a.acc + (int64_t)job * a.k * NP;
@@ -429,7 +430,19 @@ __device__ inline void assign_range(const AssignArgs& a, int job, int64_t p_begi
 
   int changed = 0;
   int par = 0;
-  for (int64_t base = p_begin; base < p_end; base += kWG * PPL) {
+  // With a claim counter the workgroups of a job share its units of kWG * PPL
+  // points dynamically: a workgroup starts with unit first_unit, and while it
+  // works on a unit thread 0 claims the next one (claim_base + the counter's
+  // value), which the end-of-unit barrier hands over.  Which workgroup takes
+  // a unit changes no result (per-chunk partials, exact integer sums,
+  // per-point labels); labels written by other workgroups are read with
+  // device-scope loads, never from L1.
+  constexpr int64_t kUnit = (int64_t)kWG * PPL;
+  __shared__ int64_t sh_next[2];
+  int64_t base = claim ? p_begin + (int64_t)first_unit * kUnit : p_begin;
+  while (base < p_end) {
+    if (claim && threadIdx.x == 0)
+      sh_next[par] = p_begin + ((int64_t)claim_base + atomicAdd(claim, 1u)) * kUnit;
     float x[PPL][NP];
     bool valid[PPL];
     int jold[PPL];
@@ -438,7 +451,10 @@ __device__ inline void assign_range(const AssignArgs& a, int job, int64_t p_begi
       const int64_t i = base + threadIdx.x + kWG * p;
       valid[p] = i < p_end;
       // previous label, loaded up front so its latency overlaps the distances
-      jold[p] = (SUMS && lab && valid[p] && !first_assign) ? lab[i] : -1;
+      jold[p] = -1;
+      if (SUMS && lab && valid[p] && !first_assign)
+        jold[p] = claim ? __hip_atomic_load(lab + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                        : lab[i];
       if (valid[p] && vec) {
         const float4* src = reinterpret_cast<const float4*>(S + i * (int64_t)NP);
 #pragma unroll
@@ -622,6 +638,7 @@ __device__ inline void assign_range(const AssignArgs& a, int job, int64_t p_begi
         }
       }
     }
+    base = claim ? sh_next[par] : base + kUnit;
     par ^= 1;
   }
 
@@ -1486,6 +1503,10 @@ size_t __host__ __device__ inline round_assign_bytes(int cp, int k) {
   return base + (size_t)k * cp * 8 + ((size_t)k * 4 + 15) / 16 * 16;
 }
 
+// Fewest Lloyd units per workgroup at which a worker's workgroups share them
+// dynamically (fewer, or one workgroup: each keeps its own range).
+constexpr int kShareUnits = 4;
+
 template <int NP, bool MF>
 __global__ __launch_bounds__(kWG, 4) void k_round(const RoundArgs* __restrict__ rp) {
   constexpr int PPL = (NP <= 32 && !MF) ? 2 : 1;
@@ -1561,6 +1582,9 @@ __global__ __launch_bounds__(kWG, 4) void k_round(const RoundArgs* __restrict__ 
   double* tf3 = r.tf3 + (int64_t)w * 3 * mc;
   unsigned long long* dl3 = r.delta + (int64_t)w * 3 * k * NP;
   int32_t* dc3 = r.dcnt + (int64_t)w * 3 * k;
+  unsigned int* claim3 = r.claim + (int64_t)w * 3;
+  // the same for every workgroup of the worker
+  const bool share = nwg > 1 && units >= (int64_t)kShareUnits * nwg;
 
   // the incumbent, kept in this workgroup's LDS
   for (int e = threadIdx.x; e < k * NP; e += kWG) {
@@ -1632,6 +1656,9 @@ __global__ __launch_bounds__(kWG, 4) void k_round(const RoundArgs* __restrict__ 
       for (int e = threadIdx.x; e < k * NP; e += kWG) sC[e] = Cp[e];
     } else {
       for (int e = threadIdx.x; e < k * NP; e += kWG) sC[e] = sI[e];
+      // shared units: rows gathered by the worker's other workgroups are read
+      // from here on (the barrier invalidates L1)
+      if (share) xcd_barrier(bar, nwg, epoch, r.err);
     }
     for (int e = threadIdx.x; e < k * NP; e += kWG) tot[e] = 0;
     for (int j = threadIdx.x; j < k; j += kWG) tcnt[j] = 0;
@@ -1643,11 +1670,19 @@ __global__ __launch_bounds__(kWG, 4) void k_round(const RoundArgs* __restrict__ 
     double f_prev = 0.0;
     for (int it = 0; it <= r.max_iter; ++it, ++ig) {
       const int b = ig % 3;
-      assign_range<NP, PPL, true, false, MF>(r.as, w, p0, p1, it == 0 ? 1 : 0, smem, true, tf3 + b * mc,
-                                  dl3 + (int64_t)b * k * NP, dc3 + b * k);
+      // the first assignment of a pass takes the points this workgroup
+      // gathered; later ones share the worker's units dynamically (rows
+      // gathered by other workgroups, read after the first barrier, which
+      // invalidates L1)
+      assign_range<NP, PPL, true, false, MF>(r.as, w, share ? 0 : p0, share ? sj : p1,
+                                             it == 0 ? 1 : 0, smem, true, tf3 + b * mc,
+                                             dl3 + (int64_t)b * k * NP, dc3 + b * k,
+                                             share ? claim3 + b : nullptr, rank, nwg);
       {  // clear the buffers of the next iteration (last read two barriers ago),
          // each workgroup its share
         const int bn = (b + 1) % 3;
+        if (leader && threadIdx.x == 0)
+          __hip_atomic_store(claim3 + bn, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const int tot_e = k * NP + k;
         const int share = (tot_e + nwg - 1) / nwg;
         const int e1 = min(tot_e, (rank + 1) * share);
