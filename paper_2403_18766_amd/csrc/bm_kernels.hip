@@ -1038,15 +1038,31 @@ __device__ __noinline__ void kpp_step_job(const KppArgs& a, int job) {
   const float* S = a.S + job * a.S_stride;
   const int lane = threadIdx.x;
   if (ks.ncand > 0) {
+    // the state's arrays are indexed by constants only (selects), so that it
+    // stays in registers instead of scratch memory
+    double pot0 = 0.0, pot1 = 0.0, pot2 = 0.0;
     for (int c = 0; c < ks.ncand; ++c) {
       const int sl = other_slot(ks.dcur, c);
-      ks.pot[c] = wave_prefix_total<double, PRE>(a.Dt + ((int64_t)sl * a.njobs + job) * a.ndt_max, ndt);
+      const double pc = wave_prefix_total<double, PRE>(a.Dt + ((int64_t)sl * a.njobs + job) * a.ndt_max, ndt);
+      pot0 = c == 0 ? pc : pot0;
+      pot1 = c == 1 ? pc : pot1;
+      pot2 = c == 2 ? pc : pot2;
     }
+    ks.pot[0] = pot0;
+    ks.pot[1] = pot1;
+    ks.pot[2] = pot2;
     int best = 0;
-    for (int c = 1; c < ks.ncand; ++c)
-      if (ks.pot[c] < ks.pot[best]) best = c;
+    double pbest = pot0;
+    if (ks.ncand > 1 && pot1 < pbest) {
+      best = 1;
+      pbest = pot1;
+    }
+    if (ks.ncand > 2 && pot2 < pbest) {
+      best = 2;
+      pbest = pot2;
+    }
     const int j = a.todo[(int64_t)job * k + ks.step - 1];
-    const int64_t istar = ks.cand[best];
+    const int64_t istar = best == 0 ? ks.cand[0] : (best == 1 ? ks.cand[1] : ks.cand[2]);
     float* cj = a.Cp + job * a.C_stride + (int64_t)j * a.cp;
     for (int d = lane; d < a.cp; d += 64) cj[d] = d < a.n ? S[istar * a.ld + d] : 0.f;
     if (lane == 0) {
@@ -1058,7 +1074,7 @@ __device__ __noinline__ void kpp_step_job(const KppArgs& a, int job) {
       }
     }
     ks.dcur = other_slot(ks.dcur, best);
-    ks.T = ks.pot[best];
+    ks.T = pbest;
     ks.has_d = 1;
     ks.ncand = 0;
   }
