@@ -1144,12 +1144,14 @@ struct ServeGroup {
   int running = 0;
   hipStream_t stream = nullptr;   // the group's own stream (groups run concurrently)
   hipEvent_t store_ev = nullptr;  // recorded after the group's latest incumbent writes
-  // job states copied after a Lloyd iteration (pinned), read one iteration
-  // later so the host never waits for the iteration it has just launched
-  JobState* snap = nullptr;
-  hipEvent_t snap_ev = nullptr;
-  std::vector<int> snap_job;  // slot_job when the copy was taken
-  bool snap_pending = false;
+  // job states copied after a Lloyd iteration (pinned, two buffers), read
+  // once the copy has completed: the host never waits for the device, and a
+  // group has at most two Lloyd iterations in flight
+  JobState* snap[2] = {nullptr, nullptr};
+  hipEvent_t snap_ev[2] = {nullptr, nullptr};
+  std::vector<int> snap_job[2];  // slot_job when each copy was taken
+  int snap_head = 0;             // oldest copy not yet read
+  int snap_count = 0;            // copies in flight
 };
 
 // Device bytes one running job of sample size s uses (sample, indices, two
@@ -1169,8 +1171,10 @@ struct ServeState {
     for (ServeGroup& g : groups) {
       if (g.c) bm_destroy(g.c);  // synchronises the group's stream
       if (g.store_ev) (void)hipEventDestroy(g.store_ev);
-      if (g.snap_ev) (void)hipEventDestroy(g.snap_ev);
-      if (g.snap) (void)hipHostFree(g.snap);
+      for (int b = 0; b < 2; ++b) {
+        if (g.snap_ev[b]) (void)hipEventDestroy(g.snap_ev[b]);
+        if (g.snap[b]) (void)hipHostFree(g.snap[b]);
+      }
       if (g.stream) (void)hipStreamDestroy(g.stream);
     }
     if (start_ev) (void)hipEventDestroy(start_ev);
@@ -1418,8 +1422,11 @@ int serve_impl(bm_ctx* c, const bm_dataset* ds, int nds, const bm_job* jobs, int
   for (ServeGroup& G : st.groups) {
     HIP_TRY(c, hipStreamCreateWithFlags(&G.stream, hipStreamNonBlocking));
     HIP_TRY(c, hipEventCreateWithFlags(&G.store_ev, hipEventDisableTiming));
-    HIP_TRY(c, hipEventCreateWithFlags(&G.snap_ev, hipEventDisableTiming));
-    HIP_TRY(c, hipHostMalloc((void**)&G.snap, (size_t)G.slots * sizeof(JobState), hipHostMallocDefault));
+    for (int b = 0; b < 2; ++b) {
+      HIP_TRY(c, hipEventCreateWithFlags(&G.snap_ev[b], hipEventDisableTiming));
+      HIP_TRY(c, hipHostMalloc((void**)&G.snap[b], (size_t)G.slots * sizeof(JobState),
+                               hipHostMallocDefault));
+    }
     HIP_TRY(c, hipStreamWaitEvent(G.stream, st.start_ev, 0));
     int rc = bm_create(c->device, G.stream, &G.c);
     if (rc != BM_OK) return c->fail(rc, "serving workspace: context creation failed");
@@ -1462,6 +1469,11 @@ int serve_impl(bm_ctx* c, const bm_dataset* ds, int nds, const bm_job* jobs, int
       const int j = order[next++];
       workers[job_worker[j]].queue.push_back(j);
     }
+    // A group with two Lloyd iterations in flight neither admits nor steps
+    // until the older one has finished on the device, so a group whose
+    // stream holds a long K-means++ chain never holds up the host loop that
+    // feeds the other groups.
+    bool progress = false;
     // admissions, earliest arrival first
     std::vector<int> heads;
     for (ServeWorker& W : workers)
@@ -1475,7 +1487,7 @@ int serve_impl(bm_ctx* c, const bm_dataset* ds, int nds, const bm_job* jobs, int
       ServeWorker& W = workers[job_worker[j]];
       ServeGroup& G = st.groups[job_group[j]];
       const int64_t bytes = serve_job_bytes(jobs[j].s, G.n, G.k);
-      if (G.running >= G.slots || inflight + bytes > sp.budget_bytes) continue;
+      if (G.snap_count >= 2 || G.running >= G.slots || inflight + bytes > sp.budget_bytes) continue;
       int q = 0;
       while (G.slot_job[q] >= 0) ++q;
       adm[job_group[j]].push_back({j, q});
@@ -1510,8 +1522,9 @@ int serve_impl(bm_ctx* c, const bm_dataset* ds, int nds, const bm_job* jobs, int
     std::vector<char> stepped(st.groups.size(), 0);
     for (size_t gi = 0; gi < st.groups.size(); ++gi) {
       ServeGroup& G = st.groups[gi];
-      if (G.running == 0) continue;
+      if (G.running == 0 || G.snap_count >= 2) continue;
       stepped[gi] = 1;
+      progress = true;
       BatchView b;
       b.first = 0;
       b.njobs = G.slots;
@@ -1531,19 +1544,24 @@ int serve_impl(bm_ctx* c, const bm_dataset* ds, int nds, const bm_job* jobs, int
     }
     ++steps;
     // finished jobs leave; an accepted result becomes the worker's incumbent.
-    // The job states read here are those copied after the previous iteration
-    // (the device meanwhile runs this one); a job finished there is inactive
-    // in this iteration's launches, which skip it.
+    // The job states read here are copies taken after earlier iterations whose
+    // copies have completed (the device meanwhile runs the later ones); a job
+    // finished there is inactive in the later launches, which skip it.
     for (size_t gi = 0; gi < st.groups.size(); ++gi) {
       ServeGroup& G = st.groups[gi];
-      if (G.snap_pending) {
-        HIP_TRY(c, hipEventSynchronize(G.snap_ev));
-        G.snap_pending = false;
+      while (G.snap_count > 0) {
+        const int h = G.snap_head;
+        const hipError_t e = hipEventQuery(G.snap_ev[h]);
+        if (e == hipErrorNotReady) break;
+        HIP_TRY(c, e);
+        G.snap_head ^= 1;
+        G.snap_count -= 1;
+        progress = true;
         bool wrote = false;
         for (int q = 0; q < G.slots; ++q) {
-          const int j = G.snap_job[q];
-          if (j < 0 || G.slot_job[q] != j || G.snap[q].active) continue;
-          const JobState& hq = G.snap[q];
+          const int j = G.snap_job[h][q];
+          if (j < 0 || G.slot_job[q] != j || G.snap[h][q].active) continue;
+          const JobState& hq = G.snap[h][q];
           ServeWorker& W = workers[job_worker[j]];
           bm_job_result& r = res[j];
           r.f = hq.f;
@@ -1576,13 +1594,16 @@ int serve_impl(bm_ctx* c, const bm_dataset* ds, int nds, const bm_job* jobs, int
         if (wrote) HIP_TRY(c, hipEventRecord(G.store_ev, G.stream));
       }
       if (G.running > 0 && stepped[gi]) {
-        G.snap_job = G.slot_job;
-        HIP_TRY(c, hipMemcpyAsync(G.snap, G.L.js, (size_t)G.slots * sizeof(JobState),
+        const int t = (G.snap_head + G.snap_count) % 2;
+        G.snap_job[t] = G.slot_job;
+        HIP_TRY(c, hipMemcpyAsync(G.snap[t], G.L.js, (size_t)G.slots * sizeof(JobState),
                                   hipMemcpyDeviceToHost, G.stream));
-        HIP_TRY(c, hipEventRecord(G.snap_ev, G.stream));
-        G.snap_pending = true;
+        HIP_TRY(c, hipEventRecord(G.snap_ev[t], G.stream));
+        G.snap_count += 1;
       }
     }
+    // every group with running jobs is still busy on the device
+    if (!progress && admitted == 0) std::this_thread::sleep_for(std::chrono::microseconds(20));
   }
   for (ServeGroup& G : st.groups) HIP_TRY(c, hipStreamSynchronize(G.stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
