@@ -379,12 +379,13 @@ BM_API int bm_get_stats(bm_ctx* ctx, bm_stats* out);
 /* Tile-size tuning of the Lloyd launches that run one assignment step per
  * launch (bm_lloyd, bm_bigmeans_run with batched = 0 or 2 or wide points;
  * bm_serve always takes the heuristic's tile size, since a timing waits for
- * the device and would hold up every other job group).  On (the default), the first batch of each (padded dimension, k,
- * log2 of its points) times one objective-mode assignment per candidate
- * tile size (a heuristic's choice, half and twice it) and keeps the fastest
- * for the context; results never depend on the tile size.  Off: the heuristic
- * alone.  Either call clears the kept choices.  Returns BM_E_ARG for a null
- * context. */
+ * the device and would hold up every other job group).  On (the default),
+ * the first batch of each (padded dimension, k, log2 of its points) times an
+ * objective-mode assignment per candidate tile size (the heuristic's choice
+ * and the sizes a quarter, half, twice and four times it, best of two timed
+ * launches after one warm-up) and keeps the fastest for the context; results
+ * never depend on the tile size.  Off: the heuristic alone.  Either call
+ * clears the kept choices.  Returns BM_E_ARG for a null context. */
 BM_API int bm_set_tuning(bm_ctx* ctx, int on);
 
 /* Host-only: the sample size of `worker` in round t under params' policy,

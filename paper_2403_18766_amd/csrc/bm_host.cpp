@@ -350,8 +350,9 @@ int tuned_tile_pts(bm_ctx* c, const BatchView& b, const std::vector<int64_t>& si
     *out = it->second;
     return BM_OK;
   }
+  // the heuristic size and two sizes either side of it (powers of two apart)
   std::vector<int> cands;
-  for (int t : {base / 2, base, base * 2})
+  for (int t : {base / 4, base / 2, base, base * 2, base * 4})
     if (t >= 2 * bm::kWG && t % (2 * bm::kWG) == 0) cands.push_back(t);
   if (!c->tev0) {
     HIP_TRY(c, hipEventCreate(&c->tev0));
@@ -381,7 +382,7 @@ int tuned_tile_pts(bm_ctx* c, const BatchView& b, const std::vector<int64_t>& si
     a.tile_job = P<int32_t>(c->tile_job);
     a.tile_idx = P<int32_t>(c->tile_idx);
     float ms = 0.f;
-    for (int rep = 0; rep < 2; ++rep) {  // the first launch warms the caches
+    for (int rep = 0; rep < 3; ++rep) {  // the first launch warms the caches; best of two
       HIP_TRY(c, hipEventRecord(c->tev0, c->stream));
       if (wide)
         HIP_TRY(c, bm::launch_assign_wide(c->stream, a, tm.total, false));
@@ -389,7 +390,9 @@ int tuned_tile_pts(bm_ctx* c, const BatchView& b, const std::vector<int64_t>& si
         HIP_TRY(c, bm::launch_assign(c->stream, a, tm.total, false));
       HIP_TRY(c, hipEventRecord(c->tev1, c->stream));
       HIP_TRY(c, hipEventSynchronize(c->tev1));
-      HIP_TRY(c, hipEventElapsedTime(&ms, c->tev0, c->tev1));
+      float r = 0.f;
+      HIP_TRY(c, hipEventElapsedTime(&r, c->tev0, c->tev1));
+      if (rep == 1 || (rep == 2 && r < ms)) ms = r;
     }
     if (t == cands.front() || ms < best_ms) {
       best_ms = ms;
