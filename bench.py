@@ -24,11 +24,14 @@ Printed (one JSON line):
   time_to_target  device seconds until Algorithm 1's final stage, applied after
                   round R, returns C with f(C, X) within 1 % of the oracle's
                   final f; assignment agreement of the final labels
+  seeds           the headline run with algorithm seeds 0-4: wall time and
+                  f(C_best, X), median / min / max
 Secondary legs: aniso28 (1,000,000 x 28, k = 25, 32 workers; HBM-bound;
 speed-up of the persistent rounds over one launch per Lloyd step and over one
 worker's sample per launch), vmf768 (2,000,000 x 768, k = 100; FP32 and BF16
 matrix cores against the oracle's f), serving (three resident 4,000,000-point
-data sets, Poisson arrivals, p50/p99 latency).
+data sets, Poisson arrivals at 2,000/s for 1 s of warm-up and 10 s measured:
+sustained jobs/s, p50/p99 latency).
 """
 
 import argparse
@@ -281,13 +284,36 @@ def c2_leg(torch, api, _lib, dev, steps, with_modes):
     return out
 
 
+def seed_spread(torch, api, Xd, P, seeds=(0, 1, 2, 3, 4)):
+    """The headline run once per algorithm seed (same data): wall time and
+    f(C_best, X) per seed, with their median, min and max."""
+    import dataclasses
+    import statistics
+    ms, fs = [], []
+    for sd in seeds:
+        log("headline run, seed", sd)
+        q = dataclasses.replace(P, seed=sd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = api.bigmeans_run(Xd, q, labels=False)
+        torch.cuda.synchronize()
+        ms.append(1e3 * (time.perf_counter() - t0))
+        fs.append(r["f_full"])
+    return {"seeds": list(seeds), "ms": ms, "f_full": fs,
+            "ms_median": statistics.median(ms), "ms_min": min(ms), "ms_max": max(ms),
+            "f_median": statistics.median(fs), "f_min": min(fs), "f_max": max(fs)}
+
+
 SERVE = dict(m=4_000_000, dims=(16, 64, 256), ks=(10, 50, 200), s_min=1024, s_max=262144,
-             workers=32, rate=2000.0, budget_gb=200)
+             workers=32, rate=2000.0, budget_gb=200, warmup_s=1.0)
 
 
-def serve_run(torch, dev, njobs):
+def serve_run(torch, dev, seconds):
     """The serving workload: Poisson arrivals of single-pass jobs against three
-    resident data sets; returns the latency summary."""
+    resident data sets for warmup_s + `seconds` seconds.  Jobs that arrive in
+    the warm-up are served but not counted; for the others: latency
+    percentiles (completion - arrival) and the sustained rate (their number
+    over the time from the first one's arrival to the last one's completion)."""
     import numpy as np
 
     from paper_2403_18766_amd import api, datagen
@@ -297,26 +323,36 @@ def serve_run(torch, dev, njobs):
     t = 0.0
     jobs = []
     ls, lb = math.log(SERVE["s_min"]), math.log(SERVE["s_max"] + 1)
-    for _ in range(njobs):
+    horizon = SERVE["warmup_s"] + seconds
+    while True:
         t += float(r.exponential(1.0 / SERVE["rate"]))
+        if t >= horizon:
+            break
         s = min(SERVE["s_max"], int(math.floor(math.exp(r.uniform(ls, lb)))))
         jobs.append(dict(arrival=t, s=s, dataset=int(r.integers(len(Xs))),
                          k=int(SERVE["ks"][r.integers(len(SERVE["ks"]))]),
                          worker=int(r.integers(SERVE["workers"])), prec=int(r.integers(2))))
-    log("serving", njobs, "jobs")
+    log("serving", len(jobs), "jobs over", horizon, "s of arrivals")
     res, st = api.serve(Xs, jobs, seed=0, budget_bytes=SERVE["budget_gb"] << 30, max_slots=64,
                         paced=True)
-    lat = np.array([x["finished"] - j["arrival"] for x, j in zip(res, jobs)]) * 1e3
+    arr = np.array([j["arrival"] for j in jobs])
+    fin = np.array([x["finished"] for x in res])
+    m = arr >= SERVE["warmup_s"]
+    lat = (fin[m] - arr[m]) * 1e3
     del Xs
     torch.cuda.empty_cache()
     return {"workload": (f"3 resident data sets of {SERVE['m']:,} points (noisy Gaussian mixtures, "
-                         f"n = 16, 64, 256); {njobs} jobs, Poisson arrivals at "
-                         f"{SERVE['rate']:.0f}/s; k in (10, 50, 200); s log-uniform in "
-                         f"[{SERVE['s_min']}, {SERVE['s_max']}]; FP32 or BF16 with equal odds (matrix-core "
-                         f"distances at n = 256); 32 workers per (data set, k); "
-                         f"{SERVE['budget_gb']} GiB budget"),
-            "jobs_per_s": njobs / st["seconds"], "p50_latency_ms": float(np.percentile(lat, 50)),
-            "p99_latency_ms": float(np.percentile(lat, 99)), "wall_s": st["seconds"],
+                         f"n = 16, 64, 256); Poisson arrivals at {SERVE['rate']:.0f}/s for "
+                         f"{SERVE['warmup_s']:g} s of warm-up + {seconds:g} s measured "
+                         f"({len(jobs)} jobs, {int(m.sum())} measured); k in (10, 50, 200); "
+                         f"s log-uniform in [{SERVE['s_min']}, {SERVE['s_max']}]; FP32 or BF16 with "
+                         f"equal odds (matrix-core distances at n = 256); 32 workers per "
+                         f"(data set, k); {SERVE['budget_gb']} GiB budget"),
+            "offered_per_s": SERVE["rate"],
+            "jobs_per_s": float(m.sum() / (fin[m].max() - arr[m].min())),
+            "p50_latency_ms": float(np.percentile(lat, 50)),
+            "p99_latency_ms": float(np.percentile(lat, 99)),
+            "jobs": len(jobs), "measured_jobs": int(m.sum()), "wall_s": st["seconds"],
             "lloyd_steps": st["steps"], "peak_running": st["peak_running"],
             "peak_bytes": st["peak_bytes"], "slot_bytes": st["slot_bytes"]}
 
@@ -391,8 +427,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-ttt", action="store_true",
                     help="skip the time-to-target run and the assignment agreement")
-    ap.add_argument("--serve-jobs", type=int, default=2000,
-                    help="jobs of the serving measurement (0 skips it)")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="measured seconds of serving arrivals after 1 s of warm-up (0 skips it)")
+    ap.add_argument("--serve-jobs", type=int, default=None,
+                    help="0 skips the serving measurement (as --serve-seconds 0)")
+    ap.add_argument("--no-seeds", action="store_true",
+                    help="skip the headline runs with algorithm seeds 0-4")
     ap.add_argument("--no-c2", action="store_true", help="skip the aniso28 leg")
     ap.add_argument("--no-modes", action="store_true",
                     help="skip the comparison with the multi-launch and plain per-sample modes")
@@ -455,6 +495,7 @@ def main():
         agree = assignment_agreement(Xh, r["Y"].cpu().numpy(), r["C_best"].cpu().numpy().astype("float64"),
                                      f_full)
         agree["gpu_near_ties"] = api.objective(Xd, r["C_best"], labels=False, near_ties=True)[2]
+    seeds = None if args.no_seeds else seed_spread(torch, api, Xd, P)
     del results
     del Xd
     torch.cuda.empty_cache()
@@ -464,7 +505,8 @@ def main():
         cpu = cpu_baseline(Xh, HEAD)
     del Xh
     c2 = None if args.no_c2 else c2_leg(torch, api, _lib, dev, 3, not args.no_modes)
-    serving = serve_run(torch, dev, args.serve_jobs) if args.serve_jobs > 0 else None
+    want_serving = args.serve_seconds > 0 and args.serve_jobs != 0
+    serving = serve_run(torch, dev, args.serve_seconds) if want_serving else None
     precision = None if args.no_precision else precision_run(torch, dev)
     out = {
         "metric": METRIC, "value": value, "unit": "dists/s", "n_gpus": 1, "steps": args.steps,
@@ -488,6 +530,7 @@ def main():
         "time_to_target": ttt,
         "f_curve": curve,
         "assignment": agree,
+        "seeds": seeds,
         "p99_latency_ms": serving["p99_latency_ms"] if serving else None,
         "aniso28": c2,
         "serving": serving,

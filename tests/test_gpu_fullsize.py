@@ -128,18 +128,19 @@ def test_serving_full_size_datasets_alone_equals_mix(dev, api, serving_host):
 
 
 def test_serving_full_size_matches_oracle_chains(dev, api, serving_host):
-    """A slice of the serving job stream on the three 4,000,000-point data sets
-    (FP32 and BF16 jobs, k in {10, 50}, samples up to 8,192 points so that the
-    FP64 replay stays short): every worker's chain of jobs is replayed with the
-    oracle's single passes of Algorithm 1 on the same data."""
+    """100 sampled jobs of the serving stream on the three 4,000,000-point data
+    sets (FP32 and BF16 jobs, k in {10, 50}, three workers per group, samples
+    of 1,024 to 4,096 points so that the FP64 replay stays short): every
+    worker's chain of jobs is replayed with the oracle's single passes of
+    Algorithm 1 on the same data."""
     from oracle import bigmeans as obm
     Xd = [to_dev(X, dev) for X in serving_host]
     r = np.random.default_rng(7)
     jobs = []
-    for _ in range(18):
-        s = int(math.floor(math.exp(r.uniform(math.log(1024), math.log(8193)))))
-        jobs.append(dict(s=min(s, 8192), dataset=int(r.integers(3)), k=int(r.choice([10, 50])),
-                         worker=int(r.integers(2)), prec=int(r.integers(2))))
+    for _ in range(100):
+        s = int(math.floor(math.exp(r.uniform(math.log(1024), math.log(4097)))))
+        jobs.append(dict(s=min(s, 4096), dataset=int(r.integers(3)), k=int(r.choice([10, 50])),
+                         worker=int(r.integers(3)), prec=int(r.integers(2))))
     say("serving full size vs oracle:", len(jobs), "jobs")
     res, _ = api.serve(Xd, jobs, seed=11, max_slots=16)
     state = {}
