@@ -346,9 +346,10 @@ typedef struct bm_serve_stats {
  *   stats     host (may be NULL).
  * Allocation: at its start, before any job runs, the call allocates the
  * incumbent store (k x n floats and k flags per worker the jobs name) and,
- * per (dataset, k, precision) group, a workspace of job slots, a stream, two
- * events and a pinned copy of the group's job states; all of it is freed
- * before the call returns.  The slots of all groups together hold at most
+ * per (dataset, k, precision) group, a workspace of job slots, a stream,
+ * three events and two pinned copies of the group's job states (read once
+ * their copy has completed: the loop never waits for the device while it has
+ * other work to issue); all of it is freed before the call returns.  The slots of all groups together hold at most
  * budget_bytes (stats->slot_bytes); every group needs at least one slot.
  * Returns BM_E_ARG for invalid jobs or a budget too small for one slot of
  * every group.  Synchronises the stream. */
