@@ -1711,22 +1711,26 @@ __global__ __launch_bounds__(kWG, 4) void k_round(const RoundArgs* __restrict__ 
       }
       xcd_barrier(bar, nwg, epoch, r.err, false);
       // every arrival's atomics and stores are complete in L2
-      {  // eight loads in flight per thread (integer sums: any order)
+      // the iteration's deltas on the first three waves, the counts and the
+      // objective's chunk partials on the last, so that every wave waits for
+      // about one round trip (integer sums: any order; f in its fixed order)
+      constexpr int kDW = kWG - 64;
+      if (threadIdx.x < kDW) {  // eight loads in flight per thread
         const unsigned long long* src = dl3 + (int64_t)b * k * NP;
         const int tot_e = k * NP;
-        for (int e0 = threadIdx.x; e0 < tot_e; e0 += 8 * kWG) {
+        for (int e0 = threadIdx.x; e0 < tot_e; e0 += 8 * kDW) {
           unsigned long long t8[8];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) t8[u] = e0 + u * kWG < tot_e ? load_dev(src + e0 + u * kWG) : 0ull;
+          for (int u = 0; u < 8; ++u) t8[u] = e0 + u * kDW < tot_e ? load_dev(src + e0 + u * kDW) : 0ull;
 #pragma unroll
           for (int u = 0; u < 8; ++u)
-            if (e0 + u * kWG < tot_e) tot[e0 + u * kWG] += (long long)t8[u];
+            if (e0 + u * kDW < tot_e) tot[e0 + u * kDW] += (long long)t8[u];
         }
-      }
-      for (int j = threadIdx.x; j < k; j += kWG) tcnt[j] += load_dev(dc3 + b * k + j);
-      if (threadIdx.x < 64) {
+      } else {
+        const int l = threadIdx.x - kDW;
+        for (int j = l; j < k; j += 64) tcnt[j] += load_dev(dc3 + b * k + j);
         const double f = wave_chunked_sum_dev(tf3 + b * mc, nch);
-        if (threadIdx.x == 0) sh_f = f;
+        if (l == 0) sh_f = f;
       }
       __syncthreads();
       const double f = sh_f;
