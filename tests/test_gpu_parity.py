@@ -439,6 +439,27 @@ def test_bigmeans_execution_modes_identical(dev, api, policy, seed):
         assert np.array_equal(a["Y"].cpu().numpy(), b["Y"].cpu().numpy())
 
 
+@pytest.mark.parametrize("k", [10, 20])
+def test_bigmeans_modes_identical_shared_units(dev, api, k):
+    # 64 workers with samples of 4,096 to 262,144 points: each XCD holds about
+    # eight of them, so in the persistent rounds the workgroups of a worker
+    # have several assignment units each and share them dynamically (claimed
+    # from a counter), while workers left with one workgroup keep their own
+    # range; the result is bitwise the one of one launch per Lloyd step
+    # (k = 10: ranking on the FP32 FMAs, two points per lane; k = 20: on the
+    # matrix cores, one point per lane)
+    X = _data("noisy28", 400_000, 4)
+    P = dict(k=k, workers=64, rounds_T=2, passes_p=2, s_min=4096, s_max=262_144, seed=40 + k,
+             size_policy=2)
+    say("bigmeans modes, shared units", X.shape, P)
+    a, b = [api.bigmeans_run(to_dev(X, dev), api.RunParams(batched=m, **P)) for m in (1, 2)]
+    assert a["f_full"] == b["f_full"] and a["s_opt"] == b["s_opt"]
+    assert a["best_worker"] == b["best_worker"] and a["lloyd_dists"] == b["lloyd_dists"]
+    assert a["lloyd_iters"] == b["lloyd_iters"] and a["improvements"] == b["improvements"]
+    assert np.array_equal(a["C_best"].cpu().numpy(), b["C_best"].cpu().numpy())
+    assert np.array_equal(a["Y"].cpu().numpy(), b["Y"].cpu().numpy())
+
+
 def test_bigmeans_execution_modes_identical_cooperative_redecision(dev, api):
     # k = 100 in 64-D: the round kernel re-decides a flagged point in one lane,
     # the per-step kernels with the whole wave -- the same values and choices
