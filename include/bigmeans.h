@@ -37,11 +37,12 @@
  *   - Sizes: 1 <= n <= 4096.  Points whose dimension rounded up to 4 is at
  *     most 64 are assigned with the point in registers and the centroids in
  *     LDS; wider points with FP32 matrix-core dot products.  k is limited by
- *     the LDS of one compute unit holding the centroids and fixed-point
- *     cluster sums: 12 k cp + 8 k bytes (cp = n rounded up to 4) plus the
- *     assignment kernel's own LDS (at most about 1.4 KB) within 160 KiB for
- *     narrow points, 516 k bytes plus 256 within 160 KiB (k <= 317) for wide
- *     ones; larger k returns BM_E_ARG.
+ *     the LDS of one compute unit: for narrow points the centroids and
+ *     fixed-point cluster sums, 12 k cp + 8 k bytes (cp = n rounded up to 4)
+ *     plus the assignment kernel's own LDS (at most about 1.4 KB) within
+ *     160 KiB; for wide ones the centroid update's label changes sorted by
+ *     cluster, 32,772 + 12 k bytes within 160 KiB (k <= 10,922); larger k
+ *     returns BM_E_ARG.
  *
  * Randomness (the paper fixes none).  Every random draw comes from the
  * Philox4x64-10 block function B(ctr, key) of Salmon et al. (SC'11) with

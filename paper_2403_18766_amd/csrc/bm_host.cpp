@@ -1016,8 +1016,8 @@ int check_dim(bm_ctx* c, int n, int k) {
   if (n > kMaxDim) return c->fail(BM_E_ARG, "n = %d exceeds the supported dimension %d", n, kMaxDim);
   if (k < 1) return c->fail(BM_E_ARG, "k must be >= 1");
   // LDS of the Lloyd-step kernels: centroids, norms and fixed-point sums
-  // (k x cp floats and int64, narrow) or the sums' 64-dimension slice (wide),
-  // plus each kernel's static LDS
+  // (k x cp floats and int64, narrow) or the update's label changes sorted by
+  // cluster (wide), plus each kernel's static LDS
   const int cp = round_up4(n);
   size_t lds = 0, st = 0;
   HIP_TRY(c, hipSetDevice(c->device));

@@ -1831,18 +1831,25 @@ hipError_t launch_assign_v(hipStream_t st, const AssignArgs& a, int ntiles, size
 // The wave re-decides its flagged points together: the sequential form
 // costs k distances per lane whenever one lane of the wave needs it, and on
 // clustered data with background noise most waves hold such a point (the
-// objective over 10,000,000 x 28 points with k = 50: 1.18 -> 0.85 ms).  The
-// per-step kernels rank on the FP32 FMAs, two points per lane up to 32
-// dimensions (measured faster than the matrix-core ranking here, whose
-// looser bound flags more points); the round kernel ranks on the matrix cores.
+// objective over 10,000,000 x 28 points with k = 50: 1.18 -> 0.85 ms).  Up to
+// 32 dimensions the per-step kernels rank on the FP32 FMAs, two points per
+// lane (measured faster than the matrix-core ranking there, whose looser
+// bound flags more points).  Wider rows hold one point per lane either way;
+// with many centres they rank on the matrix cores (n = 64: a Lloyd step with
+// k = 200 5 % faster, k = 50 2 % slower, so from one full group of 128 on).
+constexpr int kMfmaStepMinK = 128;
+
 template <int NP>
 hipError_t launch_assign_np(hipStream_t st, const AssignArgs& a, int ntiles, bool sums) {
   const size_t base = (((size_t)a.k * NP + a.k) * 4 + 15) / 16 * 16;
-  if (sums) {
-    const size_t lds = base + (size_t)a.k * NP * 8 + (size_t)a.k * 4;
-    return launch_assign_v<NP, true, true, false>(st, a, ntiles, lds);
+  const size_t lds = sums ? base + (size_t)a.k * NP * 8 + (size_t)a.k * 4 : base;
+  if constexpr (NP > 32) {
+    if (a.k >= kMfmaStepMinK)
+      return sums ? launch_assign_v<NP, true, true, true>(st, a, ntiles, lds)
+                  : launch_assign_v<NP, false, true, true>(st, a, ntiles, lds);
   }
-  return launch_assign_v<NP, false, true, false>(st, a, ntiles, base);
+  return sums ? launch_assign_v<NP, true, true, false>(st, a, ntiles, lds)
+              : launch_assign_v<NP, false, true, false>(st, a, ntiles, lds);
 }
 
 }  // namespace
@@ -1989,10 +1996,17 @@ size_t round_lds_bytes(int32_t cp, int32_t k) {
 
 template <int NP>
 hipError_t assign_static_lds_np(size_t* out) {
-  constexpr int PPL = NP <= 32 ? 2 : 1;  // the variant launched for a Lloyd step
+  // the variants launched for a Lloyd step (FMA and, above 32 dimensions,
+  // matrix-core ranking): the larger static LDS
+  constexpr int PPL = NP <= 32 ? 2 : 1;
   hipFuncAttributes fa;
   hipError_t e = hipFuncGetAttributes(&fa, (const void*)k_assign_small<NP, PPL, true, true, false>);
-  if (e == hipSuccess) *out = fa.sharedSizeBytes;
+  if (e != hipSuccess) return e;
+  *out = fa.sharedSizeBytes;
+  if constexpr (NP > 32) {
+    e = hipFuncGetAttributes(&fa, (const void*)k_assign_small<NP, 1, true, true, true>);
+    if (e == hipSuccess && fa.sharedSizeBytes > *out) *out = fa.sharedSizeBytes;
+  }
   return e;
 }
 

@@ -55,7 +55,7 @@ constexpr int kDK = 32;            // dimensions per LDS stage
 constexpr int kCG = 128;           // centres per group (four 32-wide MFMA tiles)
 constexpr int kChunk = 256;        // points per chunk (one per thread in the per-point phase)
 constexpr int kUpdDims = 64;       // dimensions per update workgroup
-constexpr int kUpdPts = 8192;      // points per update workgroup
+constexpr int kUpdPts = 4096;      // points per update workgroup
 constexpr int kUpdBatch = 16;      // changed points whose slices load together
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -785,11 +785,14 @@ __global__ __launch_bounds__(256) void k_kpp_pot_staged(KppArgs a) {
 }
 
 // Fixed-point sums of the label changes: grid (cp / 64 dimension slices,
-// point ranges of 8,192, jobs).  A point whose label went from jo to jn adds
+// point ranges of kUpdPts, jobs).  A point whose label went from jo to jn adds
 // its coordinates to cluster jn and removes them from jo (jo < 0 on the first
-// assignment); a wave handles one changed point at a time, one dimension per
-// lane.  The slice's sums gather in LDS, then go to memory with integer
-// atomics, so the result does not depend on the order.
+// assignment).  The workgroup first sorts the changes of its range by cluster
+// in LDS (a counting sort: one entry per (point, cluster, sign)), then each
+// wave walks a quarter of the sorted entries, one dimension of the slice per
+// lane, keeps the current cluster's sum in a register and adds it to memory
+// with one integer atomic per lane when the cluster changes.  Integer sums:
+// the result does not depend on the order.
 struct UpdateArgs {
   const float* S;
   int64_t S_stride;
@@ -804,7 +807,13 @@ struct UpdateArgs {
   const double* scale;      // [cp]
 };
 
-__global__ __launch_bounds__(256) void k_update_wide(UpdateArgs u) {
+// entry of the sorted changes: cluster << 13 | point in range << 1 | removal
+static_assert(kUpdPts <= 4096, "an entry holds the point's place in the range in 12 bits");
+constexpr int kUpdThreads = 512;                 // eight waves
+constexpr int kUpdWaves = kUpdThreads / 64;
+constexpr int kUpdPerThread = kUpdPts / kUpdThreads;
+
+__global__ __launch_bounds__(kUpdThreads) void k_update_wide(UpdateArgs u) {
   const int job = blockIdx.z;
   const JobState st = u.st[job];
   if (!st.active) return;
@@ -812,76 +821,116 @@ __global__ __launch_bounds__(256) void k_update_wide(UpdateArgs u) {
   const int64_t s = u.s[job];
   const int64_t r0 = (int64_t)blockIdx.y * kUpdPts;
   if (r0 >= s) return;
-  const int64_t r1 = min(s, r0 + kUpdPts);
+  const int np = (int)min((int64_t)kUpdPts, s - r0);
   const int k = u.k, d0 = blockIdx.x * kUpdDims;
   const int nd = min(kUpdDims, u.n - d0);  // real dimensions of this slice
   extern __shared__ __align__(16) unsigned char smem[];
-  unsigned long long* lacc = reinterpret_cast<unsigned long long*>(smem);
-  int* lcnt = reinterpret_cast<int*>(lacc + (size_t)k * kUpdDims);
-  for (int e = threadIdx.x; e < k * kUpdDims; e += 256) lacc[e] = 0ull;
-  for (int e = threadIdx.x; e < k; e += 256) lcnt[e] = 0;
-  __syncthreads();
-  const float* S = u.S + job * u.S_stride;
-  const int32_t* ln = ((q & 1) ? u.lab1 : u.lab0) + job * u.lab_stride;
-  const int32_t* lo = q == 0 ? nullptr : ((q & 1) ? u.lab0 : u.lab1) + job * u.lab_stride;
+  uint32_t* ent = reinterpret_cast<uint32_t*>(smem);  // [2 kUpdPts]
+  int* off = reinterpret_cast<int*>(ent + 2 * kUpdPts);  // [k + 1] counts, then offsets
+  int* cur = off + (k + 1);                                // [k] scatter cursors
+  int* dcn = cur + k;                                      // [k] count changes
   const bool counts = blockIdx.x == 0;
-  int changed = 0;
-  // each wave reads the labels of 64 consecutive points, then works through
-  // the changed ones together: lane l adds dimension d0 + l of the point
-  // (coalesced row reads, consecutive LDS words)
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const double sc = lane < nd ? u.scale[d0 + lane] : 0.0;
-  for (int64_t i0 = r0 + wv * 64; i0 < r1; i0 += 256) {
-    const int64_t i = i0 + lane;
-    int jn = -1, jo = -1;
-    if (i < r1) {
-      jn = ln[i];
-      jo = lo ? lo[i] : -1;
-    }
-    unsigned long long pend = __ballot(i < r1 && jn != jo);
-    if (pend) changed = 1;
-    while (pend) {
-      // up to kUpdBatch changed points at a time: their slices are loaded
-      // together, then added (integer sums: the order does not matter)
-      int src[kUpdBatch];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int e = tid; e <= k; e += kUpdThreads) off[e] = 0;
+  for (int e = tid; e < k; e += kUpdThreads) dcn[e] = 0;
+  // the labels of this thread's points, loaded together
+  const int32_t* ln = ((q & 1) ? u.lab1 : u.lab0) + job * u.lab_stride + r0;
+  const int32_t* lo = q == 0 ? nullptr : ((q & 1) ? u.lab0 : u.lab1) + job * u.lab_stride + r0;
+  int jn[kUpdPerThread], jo[kUpdPerThread];
 #pragma unroll
-      for (int t = 0; t < kUpdBatch; ++t) {
-        src[t] = pend ? __ffsll(pend) - 1 : -1;
-        pend &= pend - 1;
-      }
-      float xv[kUpdBatch];
+  for (int t = 0; t < kUpdPerThread; ++t) {
+    const int i = tid + t * kUpdThreads;
+    jn[t] = i < np ? ln[i] : -1;
+    jo[t] = (i < np && lo) ? lo[i] : -1;
+  }
+  __syncthreads();
+  // entries per cluster
 #pragma unroll
-      for (int t = 0; t < kUpdBatch; ++t)
-        xv[t] = (src[t] >= 0 && lane < nd) ? S[(i0 + src[t]) * (int64_t)u.ld + d0 + lane] : 0.f;
-#pragma unroll
-      for (int t = 0; t < kUpdBatch; ++t) {
-        if (src[t] < 0) break;
-        const int pn = __builtin_amdgcn_readlane(jn, src[t]);
-        const int po = __builtin_amdgcn_readlane(jo, src[t]);
-        const long long qv = quantize(xv[t], sc);
-        if (lane < nd && qv != 0) {
-          atomicAdd(&lacc[pn * kUpdDims + lane], (unsigned long long)qv);
-          if (po >= 0) atomicAdd(&lacc[po * kUpdDims + lane], (unsigned long long)(-qv));
-        }
-        if (counts && lane == 0) {
-          atomicAdd(&lcnt[pn], 1);
-          if (po >= 0) atomicAdd(&lcnt[po], -1);
-        }
+  for (int t = 0; t < kUpdPerThread; ++t) {
+    if (jn[t] != jo[t]) {
+      atomicAdd(&off[jn[t]], 1);
+      if (jo[t] >= 0) atomicAdd(&off[jo[t]], 1);
+      if (counts) {
+        atomicAdd(&dcn[jn[t]], 1);
+        if (jo[t] >= 0) atomicAdd(&dcn[jo[t]], -1);
       }
     }
   }
-  if (!__syncthreads_or(changed)) return;
-  unsigned long long* accj = u.acc + (int64_t)job * k * u.cp;
-  for (int e = threadIdx.x; e < k * kUpdDims; e += 256) {
-    const int j = e / kUpdDims, dd = e - j * kUpdDims;
-    const unsigned long long v = lacc[e];
-    if (v && dd < nd) atomicAdd(&accj[(int64_t)j * u.cp + d0 + dd], v);
+  __syncthreads();
+  // exclusive prefix over the clusters (wave 0), off[k] = number of entries
+  if (wv == 0) {
+    int carry = 0;
+    for (int c0 = 0; c0 < k; c0 += 64) {
+      const int c = c0 + lane;
+      const int v = c < k ? off[c] : 0;
+      int x = v;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+      }
+      if (c < k) {
+        off[c] = carry + x - v;
+        cur[c] = carry + x - v;
+      }
+      carry += __shfl(x, 63);
+    }
+    if (lane == 0) off[k] = carry;
   }
+  __syncthreads();
+  const int ne = off[k];
+  if (ne == 0) return;
   if (counts) {
     int32_t* cntj = u.cnt + (int64_t)job * k;
-    for (int e = threadIdx.x; e < k; e += 256)
-      if (lcnt[e]) atomicAdd(&cntj[e], lcnt[e]);
+    for (int e = tid; e < k; e += kUpdThreads)
+      if (dcn[e]) atomicAdd(&cntj[e], dcn[e]);
   }
+#pragma unroll
+  for (int t = 0; t < kUpdPerThread; ++t) {
+    if (jn[t] != jo[t]) {
+      const uint32_t pr = (uint32_t)(tid + t * kUpdThreads) << 1;
+      ent[atomicAdd(&cur[jn[t]], 1)] = ((uint32_t)jn[t] << 13) | pr;
+      if (jo[t] >= 0) ent[atomicAdd(&cur[jo[t]], 1)] = ((uint32_t)jo[t] << 13) | pr | 1u;
+    }
+  }
+  __syncthreads();
+  // this wave's share of the entries; lane l adds dimension d0 + l
+  const int per = (ne + kUpdWaves - 1) / kUpdWaves;
+  const int e0 = min(ne, wv * per), e1 = min(ne, e0 + per);
+  const float* S = u.S + job * u.S_stride + r0 * (int64_t)u.ld + d0 + lane;
+  unsigned long long* accj = u.acc + (int64_t)job * k * u.cp + d0 + lane;
+  const double sc = lane < nd ? u.scale[d0 + lane] : 0.0;
+  unsigned long long a = 0ull;
+  int cl = -1;
+  for (int b = e0; b < e1; b += 64) {
+    const uint32_t mine = b + lane < e1 ? ent[b + lane] : 0u;
+    const int nb = min(64, e1 - b);
+    for (int t0 = 0; t0 < nb; t0 += kUpdBatch) {
+      // the slices of up to kUpdBatch entries load together
+      float xv[kUpdBatch];
+#pragma unroll
+      for (int t = 0; t < kUpdBatch; ++t) {
+        const uint32_t e = __builtin_amdgcn_readlane(mine, min(t0 + t, 63));
+        xv[t] = (t0 + t < nb && lane < nd) ? S[(int64_t)((e >> 1) & 4095u) * u.ld] : 0.f;
+      }
+      unsigned long long qv[kUpdBatch];
+#pragma unroll
+      for (int t = 0; t < kUpdBatch; ++t) qv[t] = (unsigned long long)quantize(xv[t], sc);
+#pragma unroll
+      for (int t = 0; t < kUpdBatch; ++t) {
+        if (t0 + t >= nb) break;
+        const uint32_t e = __builtin_amdgcn_readlane(mine, t0 + t);
+        const int c = (int)(e >> 13);
+        if (c != cl) {
+          if (cl >= 0 && a != 0ull) atomicAdd(&accj[(int64_t)cl * u.cp], a);
+          a = 0ull;
+          cl = c;
+        }
+        a += (e & 1u) ? 0ull - qv[t] : qv[t];
+      }
+    }
+  }
+  if (cl >= 0 && a != 0ull) atomicAdd(&accj[(int64_t)cl * u.cp], a);
 }
 
 // Lloyd finalize for wide points: one workgroup per job.  Same decisions and
@@ -1020,7 +1069,7 @@ hipError_t update_wide_static_lds(size_t* out) {
 }
 
 size_t update_wide_lds(int32_t k) {
-  return (size_t)k * kUpdDims * sizeof(unsigned long long) + (size_t)k * sizeof(int);
+  return (size_t)2 * kUpdPts * sizeof(uint32_t) + ((size_t)3 * k + 1) * sizeof(int);
 }
 
 hipError_t launch_update_wide(hipStream_t st, const float* S, int64_t S_stride, int32_t ld,
@@ -1051,7 +1100,7 @@ hipError_t launch_update_wide(hipStream_t st, const float* S, int64_t S_stride, 
   }
   const dim3 grid((unsigned)((n + kUpdDims - 1) / kUpdDims),
                   (unsigned)((max_s + kUpdPts - 1) / kUpdPts), (unsigned)njobs);
-  hipLaunchKernelGGL(k_update_wide, grid, dim3(256), lds, st, u);
+  hipLaunchKernelGGL(k_update_wide, grid, dim3(kUpdThreads), lds, st, u);
   return hipGetLastError();
 }
 

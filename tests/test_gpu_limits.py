@@ -1,6 +1,7 @@
-"""Size limits of the narrow Lloyd path on the GPU: the largest k the LDS
-check admits runs (centroids, norms, fixed-point sums and the kernel's own
-LDS fit one compute unit), and the next k is refused with BM_E_ARG before
+"""Size limits of the Lloyd path on the GPU: the largest k the LDS check
+admits runs (narrow points: centroids, norms, fixed-point sums and the
+kernel's own LDS fit one compute unit; wide points: the update's label
+changes sorted by cluster), and the next k is refused with BM_E_ARG before
 any launch."""
 
 import numpy as np
@@ -44,3 +45,15 @@ def test_largest_admitted_k_runs(dev, n):
     # the objective (no sums in LDS) accepts the same k
     f, _, _ = api.objective(S, to_dev(np.ascontiguousarray(X[:lo]), dev))
     assert np.isfinite(f)
+
+
+def test_largest_admitted_k_runs_wide(dev):
+    # 32,772 + 12 k bytes of the wide update within 160 KiB: k = 10,922
+    from paper_2403_18766_amd import api
+    X = datagen.noisy_mixture(11_500, 96, 20, seed=9)
+    S = to_dev(X, dev)
+    lo = 10_922
+    say("wide n 96 largest k", lo)
+    g = _admitted(api, S, to_dev(np.ascontiguousarray(X[:lo]), dev))
+    assert g is not None and np.isfinite(g["f"])
+    assert _admitted(api, S, to_dev(np.ascontiguousarray(X[:lo + 1]), dev)) is None

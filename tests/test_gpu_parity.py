@@ -162,14 +162,15 @@ def test_objective_nan_is_reported(dev, api):
 # a3-a5: Lloyd
 # ---------------------------------------------------------------------------
 def _lloyd_case(name, m, k, seed):
-    X = _data(name, m, seed)
+    X = datagen.serving_dataset(64, m=m, seed=seed) if name == "mix64" else _data(name, m, seed)
     r = np.random.default_rng(seed + 100)
     C0 = X[r.choice(len(X), k, replace=False)].copy()
     return X, C0
 
 
 @pytest.mark.parametrize("name,m,k,seed", [("blobs2d", 2_000, 5, 0), ("aniso28", 22_161, 25, 1),
-                                           ("noisy28", 40_000, 50, 2)])
+                                           ("noisy28", 40_000, 50, 2),
+                                           ("mix64", 30_000, 150, 3)])   # matrix-core ranking
 def test_lloyd_one_update_teacher_forced(dev, api, name, m, k, seed):
     S, C0 = _lloyd_case(name, m, k, seed)
     say("lloyd one update", name, S.shape, k)
@@ -460,11 +461,13 @@ def test_bigmeans_modes_identical_shared_units(dev, api, k):
     assert np.array_equal(a["Y"].cpu().numpy(), b["Y"].cpu().numpy())
 
 
-def test_bigmeans_execution_modes_identical_cooperative_redecision(dev, api):
-    # k = 100 in 64-D: the round kernel re-decides a flagged point in one lane,
-    # the per-step kernels with the whole wave -- the same values and choices
+@pytest.mark.parametrize("k", [100, 150])
+def test_bigmeans_execution_modes_identical_cooperative_redecision(dev, api, k):
+    # k = 100 and 150 in 64-D: the round kernel re-decides a flagged point in
+    # one lane, the per-step kernels with the whole wave -- the same values and
+    # choices; at k = 150 the per-step kernels rank on the matrix cores too
     X = datagen.serving_dataset(64, m=40_000, seed=5)
-    P = dict(k=100, workers=3, rounds_T=2, passes_p=2, s_min=3000, s_max=6000, seed=21,
+    P = dict(k=k, workers=3, rounds_T=2, passes_p=2, s_min=3000, s_max=6000, seed=21,
              size_policy=2)
     say("bigmeans modes, cooperative re-decision", X.shape, P)
     runs = [api.bigmeans_run(to_dev(X, dev), api.RunParams(batched=b, **P)) for b in (1, 2, 0)]

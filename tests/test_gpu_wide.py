@@ -98,9 +98,11 @@ def test_objective_wide_ties(dev, api):
     assert not np.any(lab == 7)
 
 
-def test_lloyd_wide_one_update_teacher_forced(dev, api):
-    S = datagen.make("vmf768", m=12_000, seed=1)
-    k = 100
+@pytest.mark.parametrize("m,k", [(12_000, 100), (9_000, 600)])
+def test_lloyd_wide_one_update_teacher_forced(dev, api, m, k):
+    # the update sorts each range of 4,096 points by cluster: three ranges
+    # with a ragged last one; k = 600 has sorted runs of a few points each
+    S = datagen.make("vmf768", m=m, seed=1)
     r = np.random.default_rng(3)
     C0 = S[r.choice(len(S), k, replace=False)].copy()
     say("lloyd wide one update", S.shape, k)
@@ -121,7 +123,8 @@ def test_lloyd_wide_one_update_teacher_forced(dev, api):
     assert abs(res["f"] - fo) <= F_TOL * fo
 
 
-@pytest.mark.parametrize("s,n,k,seed", [(5_000, 768, 20, 4), (3_001, 130, 150, 5), (700, 66, 3, 6)])
+@pytest.mark.parametrize("s,n,k,seed", [(5_000, 768, 20, 4), (3_001, 130, 150, 5), (700, 66, 3, 6),
+                                        (10_000, 96, 400, 7)])
 def test_lloyd_wide_full_run(dev, api, s, n, k, seed):
     r = np.random.default_rng(seed)
     centres = r.standard_normal((k, n)) * 4
