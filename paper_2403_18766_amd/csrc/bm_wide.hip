@@ -937,7 +937,9 @@ __global__ __launch_bounds__(kUpdThreads) void k_update_wide(UpdateArgs u) {
 // arithmetic as the narrow finalize (means fp32(sum * 2^-shift / count),
 // norms as the FP64 sum of c_d^2 in dimension order), with the norms read
 // back from memory instead of LDS.
-__global__ __launch_bounds__(256) void k_finalize_wide(FinalizeArgs a) {
+constexpr int kFinThreads = 512;
+
+__global__ __launch_bounds__(kFinThreads) void k_finalize_wide(FinalizeArgs a) {
   const int job = blockIdx.x;
   JobState st = a.st[job];
   if (!st.active) return;
@@ -961,21 +963,50 @@ __global__ __launch_bounds__(256) void k_finalize_wide(FinalizeArgs a) {
   const int32_t* cnt = a.cnt + (int64_t)job * k;
   float* C = a.Cp + (int64_t)job * k * cp;
   if (upd) {
-    for (int e = threadIdx.x; e < k * cp; e += 256) {
-      const int j = e / cp, d = e - j * cp;
-      const int cj = cnt[j];
-      if (cj > 0) C[e] = (float)(((double)(long long)acc[e] * a.inv_scale[d]) / (double)cj);
+    // eight means per thread at a time, their loads issued together
+    const int kcp = k * cp;
+    for (int e0 = threadIdx.x; e0 < kcp; e0 += kFinThreads * 8) {
+      long long av[8];
+      int cv[8];
+      double sv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * kFinThreads;
+        const int j = e / cp, d = e - j * cp;
+        av[u] = e < kcp ? (long long)acc[e] : 0;
+        cv[u] = e < kcp ? cnt[j] : 0;
+        sv[u] = e < kcp ? a.inv_scale[d] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * kFinThreads;
+        if (e < kcp && cv[u] > 0) C[e] = (float)(((double)av[u] * sv[u]) / (double)cv[u]);
+      }
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < k; j += 256) {
-      const float* c = C + (int64_t)j * cp;
+    // the row's squares added in dimension order; its values are read 64 at
+    // a time (the additions form one dependent chain, so the loads must not)
+    for (int j = threadIdx.x; j < k; j += kFinThreads) {
+      const float4* c4 = reinterpret_cast<const float4*>(C + (int64_t)j * cp);
+      const int n4 = cp / 4;
       double q = 0.0;
-      for (int d = 0; d < cp; ++d) q += (double)c[d] * (double)c[d];
+      for (int b = 0; b < n4; b += 16) {
+        float4 v[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) v[t] = b + t < n4 ? c4[b + t] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+          q += (double)v[t].x * (double)v[t].x;
+          q += (double)v[t].y * (double)v[t].y;
+          q += (double)v[t].z * (double)v[t].z;
+          q += (double)v[t].w * (double)v[t].w;
+        }
+      }
       a.cn[(int64_t)job * k + j] = (float)q;
     }
   } else {
     int empty = 0;
-    for (int j = threadIdx.x; j < k; j += 256) {
+    for (int j = threadIdx.x; j < k; j += kFinThreads) {
       const int e0 = cnt[j] == 0 ? 1 : 0;
       a.deg[(int64_t)job * k + j] = (uint8_t)e0;
       empty += e0;
@@ -986,11 +1017,11 @@ __global__ __launch_bounds__(256) void k_finalize_wide(FinalizeArgs a) {
   const bool accept = sh_acc != 0;
   if (accept) {
     const int n = a.n;
-    for (int e = threadIdx.x; e < k * n; e += 256) {
+    for (int e = threadIdx.x; e < k * n; e += kFinThreads) {
       const int j = e / n, d = e - j * n;
       a.Cinc[(int64_t)job * k * n + e] = C[(int64_t)j * cp + d];
     }
-    for (int j = threadIdx.x; j < k; j += 256) a.deg_inc[(int64_t)job * k + j] = a.deg[(int64_t)job * k + j];
+    for (int j = threadIdx.x; j < k; j += kFinThreads) a.deg_inc[(int64_t)job * k + j] = a.deg[(int64_t)job * k + j];
   }
   if (threadIdx.x == 0) {
     st.f = sh_f;
@@ -1105,7 +1136,7 @@ hipError_t launch_update_wide(hipStream_t st, const float* S, int64_t S_stride, 
 }
 
 hipError_t launch_finalize_wide(hipStream_t st, const FinalizeArgs& a, int32_t njobs) {
-  hipLaunchKernelGGL(k_finalize_wide, dim3(njobs), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_finalize_wide, dim3(njobs), dim3(kFinThreads), 0, st, a);
   return hipGetLastError();
 }
 
