@@ -714,15 +714,37 @@ __device__ __noinline__ void finalize_job(const FinalizeArgs& a, int job, double
   const int32_t* cnt = a.cnt + (int64_t)job * k;
   float* C = a.Cp + (int64_t)job * k * cp;
   if (upd) {
-    for (int e = threadIdx.x; e < k * cp; e += kWG) {
-      const int j = e / cp, d = e - j * cp;
-      const int cj = cnt[j];
-      if (cj > 0) {
-        const double mean = ((double)(long long)acc[e] * a.inv_scale[d]) / (double)cj;
-        C[e] = (float)mean;
+    // eight means per thread at a time, their loads issued together (an
+    // empty cluster keeps its centroid)
+    const int kcp = k * cp;
+    for (int e0 = threadIdx.x; e0 < kcp; e0 += kWG * 8) {
+      long long av[8];
+      int cv[8];
+      double sv[8];
+      float co[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * kWG;
+        const int j = e / cp, d = e - j * cp;
+        const bool in = e < kcp;
+        av[u] = in ? (long long)acc[e] : 0;
+        cv[u] = in ? cnt[j] : 0;
+        sv[u] = in ? a.inv_scale[d] : 0.0;
+        co[u] = in ? C[e] : 0.f;
       }
-      const double cv = C[e];
-      sh_sq[e] = cv * cv;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * kWG;
+        if (e < kcp) {
+          float c = co[u];
+          if (cv[u] > 0) {
+            c = (float)(((double)av[u] * sv[u]) / (double)cv[u]);
+            C[e] = c;
+          }
+          const double x = c;
+          sh_sq[e] = x * x;
+        }
+      }
     }
     __syncthreads();
     for (int j = threadIdx.x; j < k; j += kWG) {
