@@ -708,27 +708,34 @@ __global__ __launch_bounds__(256) void k_kpp_pot_staged(KppArgs a) {
   float dcur = 0.f;
   if (i < s && ks.has_d) dcur = a.D[(int64_t)dslot * a.D_slot_stride + job * a.D_job_stride + i];
   float p[3][4] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+  // the loads of stage d0 + 32 are issued before stage d0 is computed, so they
+  // are in flight behind this workgroup's own arithmetic
+  constexpr int kPt = kChunk * (kDK / 4) / 256;
+  float4 v[kPt];
+#pragma unroll
+  for (int u = 0; u < kPt; ++u) {
+    const int e = tid + u * 256, r = e / (kDK / 4), q = e - r * (kDK / 4);
+    v[u] = stage_load(S, base + r, ld, 4 * q, n, cp, vec, r < np);
+  }
   for (int d0 = 0; d0 < cp; d0 += kDK) {
     __syncthreads();
-    {
-      constexpr int kPt = kChunk * (kDK / 4) / 256;
-      float4 v[kPt];
 #pragma unroll
-      for (int u = 0; u < kPt; ++u) {
-        const int e = tid + u * 256, r = e / (kDK / 4), q = e - r * (kDK / 4);
-        v[u] = stage_load(S, base + r, ld, d0 + 4 * q, n, cp, vec, r < np);
-      }
-#pragma unroll
-      for (int u = 0; u < kPt; ++u) {
-        const int e = tid + u * 256, r = e / (kDK / 4), q = e - r * (kDK / 4);
-        float* dst = rows + r * 33 + 4 * q;
-        dst[0] = v[u].x;
-        dst[1] = v[u].y;
-        dst[2] = v[u].z;
-        dst[3] = v[u].w;
-      }
+    for (int u = 0; u < kPt; ++u) {
+      const int e = tid + u * 256, r = e / (kDK / 4), q = e - r * (kDK / 4);
+      float* dst = rows + r * 33 + 4 * q;
+      dst[0] = v[u].x;
+      dst[1] = v[u].y;
+      dst[2] = v[u].z;
+      dst[3] = v[u].w;
     }
     __syncthreads();
+    if (d0 + kDK < cp) {
+#pragma unroll
+      for (int u = 0; u < kPt; ++u) {
+        const int e = tid + u * 256, r = e / (kDK / 4), q = e - r * (kDK / 4);
+        v[u] = stage_load(S, base + r, ld, d0 + kDK + 4 * q, n, cp, vec, r < np);
+      }
+    }
     const int dn = min(kDK, n - d0);  // real dimensions of this stage
     const float* xr = rows + tid * 33;
     for (int dd = 0; dd < dn; dd += 4) {
