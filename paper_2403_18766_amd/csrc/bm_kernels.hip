@@ -1463,6 +1463,54 @@ __device__ inline void load_row(const float* S, int64_t i, bool valid, float (&x
   }
 }
 
+// kpp_init_tile with the point's row read once into registers (NP = the
+// padded width): the distances keep dist_direct_mem's operation order, so D
+// and the tile sums are the same.  The row used to be re-read for every kept
+// centroid, which with many centroids and many waves per compute unit missed
+// L1.
+template <int NP>
+__global__ __launch_bounds__(kWG) void k_kpp_init_np(KppArgs a) {
+  const int job = kpp_job(a, blockIdx.y);
+  const int64_t tile = blockIdx.x;
+  const KppState ks = load_ks(a.ks + job);
+  if (ks.ntodo == 0 || !ks.has_d) return;
+  const int64_t s = a.s[job];
+  if (tile * kDTile >= s) return;
+  const int64_t i = tile * kDTile + threadIdx.x;
+  const bool valid = i < s;
+  const float* S = a.S + job * a.S_stride;
+  const float* C = a.Cp + job * a.C_stride;
+  const uint8_t* deg = a.deg + (int64_t)job * a.k;
+  const int n = a.n, ld = a.ld;
+  // whole 16-byte groups when every row holds NP floats at a 16-byte boundary;
+  // otherwise the first n values one by one (the others are not read below)
+  const bool vec = (ld % 4 == 0) && ld >= NP && (((uintptr_t)S & 15) == 0);
+  float x[NP];
+  if (vec) {
+    const float4* src = reinterpret_cast<const float4*>(S + (valid ? i : 0) * (int64_t)ld);
+#pragma unroll
+    for (int q = 0; q < NP / 4; ++q) {
+      const float4 v = src[q];
+      x[4 * q] = v.x;
+      x[4 * q + 1] = v.y;
+      x[4 * q + 2] = v.z;
+      x[4 * q + 3] = v.w;
+    }
+  } else {
+#pragma unroll
+    for (int d = 0; d < NP; ++d) x[d] = (valid && d < n) ? S[i * (int64_t)ld + d] : 0.f;
+  }
+  float dmin = __builtin_inff();
+  if (valid) {
+    for (int j = 0; j < a.k; ++j)
+      if (!deg[j]) dmin = min_nan(dmin, dist_direct_regn<NP>(x, C + (int64_t)j * a.cp, n));
+    a.D[0 * a.D_slot_stride + job * a.D_job_stride + i] = dmin;
+  }
+  __shared__ double red[4];
+  const double ts = block_sum_f64(valid ? (double)dmin : 0.0, red);
+  if (threadIdx.x == 0) a.Dt[(0 * (int64_t)a.njobs + job) * a.ndt_max + tile] = ts;
+}
+
 // K-means++ in the persistent kernel: the same values as kpp_init_tile and
 // kpp_pot_tile for the tiles [c0, c1) of one worker, with the workgroup's
 // points in registers, the centres (the incumbent in LDS) or the candidate
@@ -2063,8 +2111,20 @@ hipError_t launch_kpp_setup(hipStream_t st, const KppArgs& a, int32_t njobs) {
   return hipGetLastError();
 }
 
+template <int NP>
+hipError_t launch_kpp_init_np(hipStream_t st, const KppArgs& a, dim3 grid) {
+  hipLaunchKernelGGL(k_kpp_init_np<NP>, grid, dim3(kWG), 0, st, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_kpp_init(hipStream_t st, const KppArgs& a, int32_t njobs, int64_t max_s) {
   const dim3 grid((unsigned)((max_s + kDTile - 1) / kDTile), (unsigned)njobs);
+  const int cp = a.cp;
+  if (cp >= 4 && cp <= kMaxRegDim && cp % 4 == 0) {
+#define BM_KI(NPV) launch_kpp_init_np<NPV>(st, a, grid)
+    BM_ROUND_SWITCH(BM_KI)
+#undef BM_KI
+  }
   hipLaunchKernelGGL(k_kpp_init, grid, dim3(kWG), 0, st, a);
   return hipGetLastError();
 }
