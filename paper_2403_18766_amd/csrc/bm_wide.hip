@@ -795,9 +795,9 @@ __global__ __launch_bounds__(256) void k_kpp_pot_staged(KppArgs a) {
 // point ranges of kUpdPts, jobs).  A point whose label went from jo to jn adds
 // its coordinates to cluster jn and removes them from jo (jo < 0 on the first
 // assignment).  The workgroup first sorts the changes of its range by cluster
-// in LDS (a counting sort: one entry per (point, cluster, sign)), then each
-// wave walks a quarter of the sorted entries, one dimension of the slice per
-// lane, keeps the current cluster's sum in a register and adds it to memory
+// in LDS (a counting sort: one entry per (point, cluster, sign)), then each of
+// its eight waves walks an eighth of the sorted entries, one dimension of the
+// slice per lane, keeps the current cluster's sum in a register and adds it to memory
 // with one integer atomic per lane when the cluster changes.  Integer sums:
 // the result does not depend on the order.
 struct UpdateArgs {

@@ -98,10 +98,11 @@ def test_objective_wide_ties(dev, api):
     assert not np.any(lab == 7)
 
 
-@pytest.mark.parametrize("m,k", [(12_000, 100), (9_000, 600)])
+@pytest.mark.parametrize("m,k", [(12_000, 100), (9_000, 600), (8_192, 50), (4_097, 30)])
 def test_lloyd_wide_one_update_teacher_forced(dev, api, m, k):
     # the update sorts each range of 4,096 points by cluster: three ranges
-    # with a ragged last one; k = 600 has sorted runs of a few points each
+    # with a ragged last one; k = 600 has sorted runs of a few points each;
+    # two whole ranges; a last range of one point
     S = datagen.make("vmf768", m=m, seed=1)
     r = np.random.default_rng(3)
     C0 = S[r.choice(len(S), k, replace=False)].copy()
@@ -124,7 +125,7 @@ def test_lloyd_wide_one_update_teacher_forced(dev, api, m, k):
 
 
 @pytest.mark.parametrize("s,n,k,seed", [(5_000, 768, 20, 4), (3_001, 130, 150, 5), (700, 66, 3, 6),
-                                        (10_000, 96, 400, 7)])
+                                        (10_000, 96, 400, 7), (1, 70, 1, 8), (5, 130, 5, 9)])
 def test_lloyd_wide_full_run(dev, api, s, n, k, seed):
     r = np.random.default_rng(seed)
     centres = r.standard_normal((k, n)) * 4
