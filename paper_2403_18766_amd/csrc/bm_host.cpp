@@ -256,13 +256,15 @@ int ensure_objective(bm_ctx* c, int64_t m) {
 
 // Points per assignment workgroup: a multiple of 512 (two 256-point chunks,
 // one per register-blocked point of a lane), large enough that the whole
-// batch fits in about 1,024 workgroups, i.e. one residency round of the
-// chip (256 compute units x 4 workgroups at the kernel's register use).
+// batch fits in about 2,048 workgroups, two residency rounds of the chip
+// (256 compute units x 4 workgroups at the kernel's register use), so that
+// the second round evens out the first one's uneven finishing times (serving
+// measured 2 % faster than with one round, and 3 % slower with half a round).
 int choose_tile_pts(const std::vector<int64_t>& sizes) {
   int64_t total = 0;
   for (int64_t s : sizes) total += s;
   const int64_t step = 2 * bm::kWG;
-  const int64_t target = 1024;
+  const int64_t target = 2048;
   int64_t steps = (total + step * target - 1) / (step * target);
   steps = std::max<int64_t>(steps, 1);
   return (int)(steps * step);
