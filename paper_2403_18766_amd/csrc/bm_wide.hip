@@ -54,6 +54,7 @@ namespace {
 constexpr int kDK = 32;            // dimensions per LDS stage
 constexpr int kCG = 128;           // centres per group (four 32-wide MFMA tiles)
 constexpr int kChunk = 256;        // points per chunk (one per thread in the per-point phase)
+constexpr int kPotDK = 32;         // dimensions per LDS stage of the K-means++ potentials
 constexpr int kUpdDims = 64;       // dimensions per update workgroup
 constexpr int kUpdPts = 4096;      // points per update workgroup
 constexpr int kUpdBatch = 16;      // changed points whose slices load together
@@ -697,7 +698,7 @@ __global__ __launch_bounds__(256) void k_kpp_pot_staged(KppArgs a) {
   const int vec = (ld % 4 == 0 && (((uintptr_t)S & 15) == 0)) ? 1 : 0;
   extern __shared__ __align__(16) float kpp_lds[];
   float* cand = kpp_lds;              // [3][cp]
-  float* rows = kpp_lds + 3 * cp;     // [256][33]
+  float* rows = kpp_lds + 3 * cp;     // [256][kPotDK + 1]
   __shared__ double red[12];
   for (int e = tid; e < 3 * cp; e += 256) {  // rows of absent candidates are zero
     const int c = e / cp, d = e - c * cp;
@@ -710,34 +711,34 @@ __global__ __launch_bounds__(256) void k_kpp_pot_staged(KppArgs a) {
   float p[3][4] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
   // the loads of stage d0 + 32 are issued before stage d0 is computed, so they
   // are in flight behind this workgroup's own arithmetic
-  constexpr int kPt = kChunk * (kDK / 4) / 256;
+  constexpr int kPt = kChunk * (kPotDK / 4) / 256;
   float4 v[kPt];
 #pragma unroll
   for (int u = 0; u < kPt; ++u) {
-    const int e = tid + u * 256, r = e / (kDK / 4), q = e - r * (kDK / 4);
+    const int e = tid + u * 256, r = e / (kPotDK / 4), q = e - r * (kPotDK / 4);
     v[u] = stage_load(S, base + r, ld, 4 * q, n, cp, vec, r < np);
   }
-  for (int d0 = 0; d0 < cp; d0 += kDK) {
+  for (int d0 = 0; d0 < cp; d0 += kPotDK) {
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < kPt; ++u) {
-      const int e = tid + u * 256, r = e / (kDK / 4), q = e - r * (kDK / 4);
-      float* dst = rows + r * 33 + 4 * q;
+      const int e = tid + u * 256, r = e / (kPotDK / 4), q = e - r * (kPotDK / 4);
+      float* dst = rows + r * (kPotDK + 1) + 4 * q;
       dst[0] = v[u].x;
       dst[1] = v[u].y;
       dst[2] = v[u].z;
       dst[3] = v[u].w;
     }
     __syncthreads();
-    if (d0 + kDK < cp) {
+    if (d0 + kPotDK < cp) {
 #pragma unroll
       for (int u = 0; u < kPt; ++u) {
-        const int e = tid + u * 256, r = e / (kDK / 4), q = e - r * (kDK / 4);
-        v[u] = stage_load(S, base + r, ld, d0 + kDK + 4 * q, n, cp, vec, r < np);
+        const int e = tid + u * 256, r = e / (kPotDK / 4), q = e - r * (kPotDK / 4);
+        v[u] = stage_load(S, base + r, ld, d0 + kPotDK + 4 * q, n, cp, vec, r < np);
       }
     }
-    const int dn = min(kDK, n - d0);  // real dimensions of this stage
-    const float* xr = rows + tid * 33;
+    const int dn = min(kPotDK, n - d0);  // real dimensions of this stage
+    const float* xr = rows + tid * (kPotDK + 1);
     for (int dd = 0; dd < dn; dd += 4) {
       const int d = d0 + dd;
       if (d + 4 <= n4) {
@@ -1089,7 +1090,7 @@ hipError_t launch_kpp_init_wide(hipStream_t st, const AssignArgs& a, int32_t nti
 
 hipError_t launch_kpp_pot_staged(hipStream_t st, const KppArgs& a, int32_t njobs, int64_t max_s) {
   const dim3 grid((unsigned)((max_s + kChunk - 1) / kChunk), (unsigned)njobs);
-  const size_t lds = ((size_t)3 * a.cp + (size_t)kChunk * 33) * sizeof(float);
+  const size_t lds = ((size_t)3 * a.cp + (size_t)kChunk * (kPotDK + 1)) * sizeof(float);
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)k_kpp_pot_staged,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
